@@ -1,0 +1,131 @@
+"""CPU oracle for the sort: plain C counting sort behind ctypes.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+``bench.py``'s ``cpu_baseline`` leg may import this package.  The product
+path (``paper_2605_10390_amd``) never imports it.
+
+Each function follows a passage of the paper (arXiv 2605.10390):
+  histogram       -- leaf counters of a digit (Sec. III-B.1, Alg. 1)
+  exclusive_scan  -- GetIndex as the exclusive prefix (Alg. 3)
+  select          -- GetItem as an order-statistic walk (Alg. 2)
+  expand          -- the sorted array written out from a full-width
+                     histogram (Alg. 5 with no trailing bits)
+  sort            -- histogram / prefix / stable scatter radix sort
+                     (Sec. II), least-significant 8-bit digit first
+  sort_segments   -- independent sorts of back-to-back segments
+Every function is pinned by tests/test_oracle_pins.py against brute force,
+closed forms and library routines; none is "parity unpinned".
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_KEY_DTYPES = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+
+
+def load(path=None, rebuild_if_missing=True):
+    """Load liboracle.so (compiling it with gcc when it is missing)."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    p = path or _build.LIB
+    if not os.path.exists(p):
+        if not rebuild_if_missing:
+            raise FileNotFoundError(p)
+        _build.build(p)
+    lib = ctypes.CDLL(p)
+    u64, vp, i32 = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+    lib.oracle_histogram.argtypes = [vp, u64, i32, i32, i32, vp]
+    lib.oracle_histogram.restype = i32
+    lib.oracle_exclusive_scan.argtypes = [vp, u64, vp]
+    lib.oracle_exclusive_scan.restype = i32
+    lib.oracle_select.argtypes = [vp, u64, u64]
+    lib.oracle_select.restype = u64
+    lib.oracle_expand.argtypes = [vp, u64, vp, i32]
+    lib.oracle_expand.restype = i32
+    lib.oracle_sort.argtypes = [vp, vp, vp, vp, u64, i32, i32]
+    lib.oracle_sort.restype = i32
+    lib.oracle_sort_segments.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp, i32]
+    lib.oracle_sort_segments.restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def histogram(keys, shift, bits, lib=None):
+    """Counts of the `bits`-wide digit at bit `shift`: uint64[2**bits]."""
+    lib = lib or load()
+    keys = np.ascontiguousarray(keys)
+    h = np.zeros(1 << bits, dtype=np.uint64)
+    _check(lib.oracle_histogram(_ptr(keys), keys.size, keys.itemsize, shift, bits, _ptr(h)),
+           "histogram")
+    return h
+
+
+def exclusive_scan(hist, lib=None):
+    """prefix[b] = sum(hist[:b]); the extra last entry is the total."""
+    lib = lib or load()
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    p = np.zeros(hist.size + 1, dtype=np.uint64)
+    _check(lib.oracle_exclusive_scan(_ptr(hist), hist.size, p.ctypes.data_as(ctypes.c_void_p)),
+           "exclusive_scan")
+    return p
+
+
+def select(hist, index, lib=None):
+    """Value at sorted position `index`; len(hist) when out of range."""
+    lib = lib or load()
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    return int(lib.oracle_select(_ptr(hist), hist.size, int(index)))
+
+
+def expand(hist, key_dtype, lib=None):
+    """Sorted array implied by a histogram over every key value."""
+    lib = lib or load()
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    out = np.empty(int(hist.sum()), dtype=key_dtype)
+    _check(lib.oracle_expand(_ptr(hist), hist.size, _ptr(out), out.itemsize), "expand")
+    return out
+
+
+def sort(keys, vals=None, lib=None):
+    """Stable ascending sort; returns keys_out or (keys_out, vals_out)."""
+    lib = lib or load()
+    keys = np.ascontiguousarray(keys)
+    ko = np.empty_like(keys)
+    if vals is None:
+        _check(lib.oracle_sort(_ptr(keys), _ptr(ko), None, None, keys.size, keys.itemsize, 0),
+               "sort")
+        return ko
+    vals = np.ascontiguousarray(vals)
+    if vals.size != keys.size:
+        raise ValueError("keys and vals differ in length")
+    vo = np.empty_like(vals)
+    _check(lib.oracle_sort(_ptr(keys), _ptr(ko), _ptr(vals), _ptr(vo), keys.size,
+                           keys.itemsize, vals.itemsize), "sort")
+    return ko, vo
+
+
+def sort_segments(segments, lib=None):
+    """Sort each (keys[, vals]) array of `segments` independently."""
+    out = []
+    for seg in segments:
+        if isinstance(seg, tuple):
+            out.append(sort(seg[0], seg[1], lib=lib))
+        else:
+            out.append(sort(seg, lib=lib))
+    return out
