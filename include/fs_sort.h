@@ -1,0 +1,134 @@
+/*
+ * fs_sort.h -- C ABI of the MI355X (gfx950) compressed-histogram radix sort.
+ *
+ * The operation is the one stated in "FractalSortCPU: Bandwidth-Efficient
+ * Compressed Radix Sort on CPU" (arXiv 2605.10390): sort n keys of p bits.
+ * Section II splits radix sorting into a histogram phase, a prefix-sum phase
+ * and a stable scatter phase; Section III builds the histogram as a tree of
+ * narrow counters (Fractal RMW, Algorithm 1; counter width tapering,
+ * Section III-D.1), reads ranks from it as prefix sums (GetIndex,
+ * Algorithm 3) and, when the histogram covers every key bit, writes the
+ * sorted array straight from it (Algorithm 5).  Where the paper is silent
+ * this library fixes: keys are unsigned integers, order is ascending, and
+ * payloads follow their keys stably (equal keys keep their input order), so
+ * every result is unique.
+ *
+ * Conventions shared by every call:
+ *   - Pointers named d_* / keys_* / vals_* / workspace are DEVICE pointers
+ *     (hipMalloc memory of the current device).  Arrays are dense and
+ *     little-endian: element i of a key array sits at byte i * key_bits/8.
+ *   - The caller owns every buffer, including the workspace.  The library
+ *     never allocates or frees caller memory and keeps no pointer after a
+ *     call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *     enqueue work on it and return without synchronising; results are
+ *     ready when the stream reaches that point.  Calls on different streams
+ *     with different workspaces may run concurrently.
+ *   - Workspace query: pass workspace == NULL and the call writes the number
+ *     of workspace bytes it needs to *workspace_bytes, launches nothing and
+ *     returns FS_OK.  Otherwise *workspace_bytes is the size of the buffer
+ *     passed; too small gives FS_ERR_WORKSPACE_TOO_SMALL.  The workspace
+ *     must be 256-byte aligned.  Its contents on entry do not matter; on
+ *     exit its first 32-bit word is 0 unless a device-side bounded wait gave
+ *     up (a library defect), in which case the output is not valid.
+ *   - Errors are status codes; nothing aborts.  A NULL pointer with n > 0,
+ *     an unsupported width, overlapping input and output ranges, or an
+ *     unaligned workspace give FS_ERR_INVALID_ARG and launch nothing.  A
+ *     failed kernel launch gives FS_ERR_DEVICE.  n == 0 is FS_OK and a
+ *     no-op.  n may be as large as 2^36.
+ */
+#ifndef FS_SORT_H
+#define FS_SORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FS_OK = 0,
+    FS_ERR_INVALID_ARG = 1,
+    FS_ERR_UNSUPPORTED = 2,
+    FS_ERR_WORKSPACE_TOO_SMALL = 3,
+    FS_ERR_DEVICE = 4
+} fs_status;
+
+enum { FS_FLAG_NONE = 0 };
+
+/*
+ * Stable ascending sort of n unsigned keys (Section II phases; for 16-bit
+ * keys the whole sort is the compressed 2^16-bin histogram written out in
+ * order, Algorithm 5 with no trailing bits).
+ *   keys_in   device, n keys of key_bits bits (16, 32 or 64); not modified.
+ *   keys_out  device, n keys; must not overlap keys_in.
+ */
+fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_bits,
+                       unsigned flags, void *workspace, size_t *workspace_bytes, void *stream);
+
+/*
+ * Stable ascending sort of n (key, value) pairs: keys_out is keys_in in
+ * ascending order and vals_out[i] is the value that came with keys_out[i];
+ * equal keys keep their input order.  With vals_in[i] = i, vals_out is the
+ * paper's index array (sorted position -> arrival position, Section III-G.3).
+ *   keys_in/keys_out  device, n keys of key_bits bits (16, 32, 64).
+ *   vals_in/vals_out  device, n values of val_bytes bytes (4 or 8).
+ * None of the four ranges may overlap another.
+ */
+fs_status fs_sort_pairs(const void *keys_in, void *keys_out, const void *vals_in, void *vals_out,
+                        uint64_t n, int key_bits, int val_bytes, unsigned flags,
+                        void *workspace, size_t *workspace_bytes, void *stream);
+
+/*
+ * Leaf counters of every digit of the keys (the histogram of Section III-B,
+ * Algorithm 1, merged across workgroups as in Section III-A.1/III-B):
+ *   hist_out[j * 2^digit_bits + b] = #{ i : bits [j*digit_bits,
+ *                                        (j+1)*digit_bits) of key i == b }
+ * for j in [0, key_bits / digit_bits).  digit_bits is 8 or 16 (16 only for
+ * 16-bit keys, which uses the compressed 2^16-bin histogram).  hist_out is a
+ * device array of uint64 written in full.
+ */
+fs_status fs_digit_histograms(const void *keys, uint64_t n, int key_bits, int digit_bits,
+                              uint64_t *hist_out, void *workspace, size_t *workspace_bytes,
+                              void *stream);
+
+/*
+ * One segment of a batched segmented sort.  keys_in/keys_out (and
+ * vals_in/vals_out when vals_in is not NULL) are device pointers to n
+ * elements; key_bits is 16, 32 or 64; val_bytes is 0 (keys only), 4 or 8.
+ */
+typedef struct {
+    const void *keys_in;
+    void *keys_out;
+    const void *vals_in;
+    void *vals_out;
+    uint64_t n;
+    uint32_t key_bits;
+    uint32_t val_bytes;
+} fs_segment;
+
+/*
+ * Many independent sorts in one call (each segment's result is exactly what
+ * fs_sort_keys / fs_sort_pairs gives for it alone).  Batching follows the
+ * paper's batch processing (Sections III-C, IV-D): segments are binned by
+ * length on the device and drained by persistent workgroups.
+ *   d_segments        DEVICE array of num_segments descriptors, read on the
+ *                     device (it may be written by earlier stream work).
+ *   total_keys        sum of the segments' n (host-known, for sizing).
+ *   max_segment_keys  the largest n (host-known, for sizing).
+ * Segments may mix key widths and payload widths.  A segment's buffers must
+ * not overlap each other or another segment's.
+ */
+fs_status fs_sort_segmented(const fs_segment *d_segments, uint32_t num_segments,
+                            uint64_t total_keys, uint64_t max_segment_keys, unsigned flags,
+                            void *workspace, size_t *workspace_bytes, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *fs_status_string(fs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FS_SORT_H */

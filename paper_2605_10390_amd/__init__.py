@@ -1,0 +1,186 @@
+"""Python binding of libfsort.so, the MI355X compressed-histogram radix sort.
+
+Argument marshalling only: every step of a sort runs in the HIP kernels
+behind include/fs_sort.h.  PyTorch supplies device memory and the current
+stream.  There is no CPU fallback: if the HIP library is missing, every call
+raises.
+
+Keys are unsigned 16/32/64-bit integers (torch.uint16/uint32/uint64, or the
+signed dtypes of the same width, whose bits are then read as unsigned);
+values are 4- or 8-byte integers.  Results are ascending and stable.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsort.so")
+
+FS_OK, FS_ERR_INVALID_ARG, FS_ERR_UNSUPPORTED, FS_ERR_WORKSPACE_TOO_SMALL, FS_ERR_DEVICE = range(5)
+
+_KEY_BITS = {torch.uint16: 16, torch.int16: 16, torch.uint32: 32, torch.int32: 32,
+             torch.uint64: 64, torch.int64: 64}
+_VAL_BYTES = {torch.uint32: 4, torch.int32: 4, torch.float32: 4, torch.uint64: 8,
+              torch.int64: 8, torch.float64: 8}
+
+_lib = None
+
+
+class FsError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+def lib():
+    """The loaded HIP library (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build(); "
+                           "there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    L.fs_sort_keys.argtypes = [vp, vp, u64, i32, ctypes.c_uint, vp, sz, vp]
+    L.fs_sort_keys.restype = i32
+    L.fs_sort_pairs.argtypes = [vp, vp, vp, vp, u64, i32, i32, ctypes.c_uint, vp, sz, vp]
+    L.fs_sort_pairs.restype = i32
+    L.fs_digit_histograms.argtypes = [vp, u64, i32, i32, vp, vp, sz, vp]
+    L.fs_digit_histograms.restype = i32
+    L.fs_sort_segmented.argtypes = [vp, u32, u64, u64, ctypes.c_uint, vp, sz, vp]
+    L.fs_sort_segmented.restype = i32
+    L.fs_status_string.argtypes = [i32]
+    L.fs_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return lib().fs_status_string(int(status)).decode()
+
+
+def _stream(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("tensors must live on the GPU (no CPU fallback)")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _key_bits(keys):
+    if keys.dtype not in _KEY_BITS:
+        raise TypeError(f"unsupported key dtype {keys.dtype}")
+    return _KEY_BITS[keys.dtype]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(None)
+
+
+class Workspace:
+    """Reusable device workspace (grows on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def error_word(self):
+        """Device error word of the last call (0 = ok); synchronises."""
+        if self.buf is None:
+            return 0
+        return int(self.buf[:4].view(torch.int32).item())
+
+
+def sort_keys_workspace_bytes(n, key_bits):
+    size = ctypes.c_size_t(0)
+    st = lib().fs_sort_keys(None, None, int(n), int(key_bits), 0, None, ctypes.byref(size), None)
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_keys (workspace query)")
+    return size.value
+
+
+def sort_pairs_workspace_bytes(n, key_bits, val_bytes):
+    size = ctypes.c_size_t(0)
+    st = lib().fs_sort_pairs(None, None, None, None, int(n), int(key_bits), int(val_bytes), 0,
+                             None, ctypes.byref(size), None)
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_pairs (workspace query)")
+    return size.value
+
+
+def sort_keys(keys, out=None, workspace=None):
+    """Ascending sort of a 1-D tensor of unsigned keys (returns `out`)."""
+    _check_dev(keys)
+    bits = _key_bits(keys)
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_dev(out)
+    ws = workspace or Workspace(keys.device)
+    need = sort_keys_workspace_bytes(n, bits)
+    buf = ws.get(need)
+    size = ctypes.c_size_t(buf.numel())
+    st = lib().fs_sort_keys(_ptr(keys), _ptr(out), n, bits, 0, _ptr(buf), ctypes.byref(size),
+                            _stream(keys))
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_keys")
+    return out
+
+
+def sort_pairs(keys, vals, keys_out=None, vals_out=None, workspace=None):
+    """Stable ascending sort of (key, value) pairs; returns (keys, values)."""
+    _check_dev(keys, vals)
+    bits = _key_bits(keys)
+    if vals.dtype not in _VAL_BYTES:
+        raise TypeError(f"unsupported value dtype {vals.dtype}")
+    vb = _VAL_BYTES[vals.dtype]
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and values differ in length")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    _check_dev(keys_out, vals_out)
+    ws = workspace or Workspace(keys.device)
+    buf = ws.get(sort_pairs_workspace_bytes(n, bits, vb))
+    size = ctypes.c_size_t(buf.numel())
+    st = lib().fs_sort_pairs(_ptr(keys), _ptr(keys_out), _ptr(vals), _ptr(vals_out), n, bits, vb,
+                             0, _ptr(buf), ctypes.byref(size), _stream(keys))
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_pairs")
+    return keys_out, vals_out
+
+
+def digit_histograms(keys, digit_bits=8, workspace=None):
+    """Counts of every digit value: int64 tensor [key_bits/digit_bits, 2**digit_bits]
+    (uint64 counts; they never reach 2^63)."""
+    _check_dev(keys)
+    bits = _key_bits(keys)
+    n = keys.numel()
+    digits = bits // digit_bits
+    out = torch.empty(digits, 1 << digit_bits, dtype=torch.int64, device=keys.device)
+    size = ctypes.c_size_t(0)
+    L = lib()
+    st = L.fs_digit_histograms(None, n, bits, digit_bits, None, None, ctypes.byref(size), None)
+    if st != FS_OK:
+        raise FsError(st, "fs_digit_histograms (workspace query)")
+    ws = workspace or Workspace(keys.device)
+    buf = ws.get(size.value)
+    size = ctypes.c_size_t(buf.numel())
+    st = L.fs_digit_histograms(_ptr(keys), n, bits, digit_bits, _ptr(out), _ptr(buf),
+                               ctypes.byref(size), _stream(keys))
+    if st != FS_OK:
+        raise FsError(st, "fs_digit_histograms")
+    return out

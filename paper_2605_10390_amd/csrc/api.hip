@@ -1,0 +1,258 @@
+// C ABI entry points (include/fs_sort.h): argument checks, workspace layout
+// and the launch sequence of each call.  Host code only.
+#include "fs_sort.h"
+#include "fs_device.hpp"
+#include "fs_internal.hpp"
+
+#include <algorithm>
+
+namespace fs {
+
+int device_cu_count() {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+        return 256;
+    return c;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
+    SortLayout L;
+    L.key_bytes = key_bytes;
+    L.val_bytes = val_bytes;
+    L.digits = key_bytes;  // 8-bit digits
+    L.expand16 = key_bytes == 2 && val_bytes == 0;
+    L.compressed16 = key_bytes == 2;
+    if (L.compressed16)
+        L.hist_groups = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), num_cus);
+    else
+        L.hist_groups = (uint32_t)std::min<uint64_t>(
+            std::max<uint64_t>(ceil_div(n, (uint64_t)kHist8Threads * 16), 1), 2ull * num_cus);
+    const uint64_t T = scatter_shape(key_bytes, val_bytes).tile();
+    L.portions = (uint32_t)std::max<uint64_t>(ceil_div(n, kPortionKeys), 1);
+    L.tiles_per_portion = (uint32_t)std::max<uint64_t>(ceil_div(std::min<uint64_t>(n, kPortionKeys), T), 1);
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    L.err = take(4 + 4ull * 8 * L.portions);  // error word, then one ticket per (pass, portion)
+    L.tickets = L.err + 4;
+    L.plan = take(4ull * kPlanWords);
+    L.hist = take(8ull * 8 * kRadix);
+    L.base = take(8ull * 8 * 2 * kRadix);
+    if (L.compressed16) {
+        L.part = take(4ull * L.hist_groups * kHist16Words);
+        L.wrap = take(4ull * 2 * kHist16Words);
+        L.h16 = take(8ull * 65536);
+        L.p16 = take(8ull * 65537);
+    } else {
+        L.part = take(4ull * L.hist_groups * L.digits * kRadix);
+    }
+    if (!L.expand16) {
+        L.state = take(4ull * kRadix * L.tiles_per_portion);
+        L.tmp_keys = take((size_t)n * key_bytes);
+        if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
+    }
+    L.total = off;
+    return L;
+}
+
+static bool overlaps(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
+static bool aligned(const void* p, uint64_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+constexpr uint64_t kMaxKeys = 1ull << 36;
+
+#define FS_TRY(expr)                                   \
+    do {                                               \
+        if ((expr) != hipSuccess) return FS_ERR_DEVICE; \
+    } while (0)
+
+static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                           uint64_t n, int key_bits, int val_bytes, void* workspace,
+                           size_t* workspace_bytes, hipStream_t s) {
+    if (key_bits != 16 && key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
+    if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
+    if (!workspace_bytes || n > kMaxKeys) return FS_ERR_INVALID_ARG;
+    const int kb = key_bits / 8;
+    const SortLayout L = sort_layout(n, kb, val_bytes, device_cu_count());
+    if (!workspace) {
+        *workspace_bytes = L.total;
+        return FS_OK;
+    }
+    if (n == 0) return FS_OK;
+    if (!keys_in || !keys_out || (val_bytes && (!vals_in || !vals_out))) return FS_ERR_INVALID_ARG;
+    if (!aligned(keys_in, kb) || !aligned(keys_out, kb) || !aligned(workspace, 256))
+        return FS_ERR_INVALID_ARG;
+    if (val_bytes && (!aligned(vals_in, val_bytes) || !aligned(vals_out, val_bytes)))
+        return FS_ERR_INVALID_ARG;
+    const uint64_t kbytes = n * kb, vbytes = n * val_bytes;
+    if (overlaps(keys_in, kbytes, keys_out, kbytes)) return FS_ERR_INVALID_ARG;
+    if (val_bytes) {
+        if (overlaps(vals_in, vbytes, vals_out, vbytes) || overlaps(keys_in, kbytes, vals_in, vbytes) ||
+            overlaps(keys_out, kbytes, vals_out, vbytes) || overlaps(keys_in, kbytes, vals_out, vbytes) ||
+            overlaps(keys_out, kbytes, vals_in, vbytes))
+            return FS_ERR_INVALID_ARG;
+    }
+    if (*workspace_bytes < L.total) return FS_ERR_WORKSPACE_TOO_SMALL;
+    if (overlaps(workspace, L.total, keys_out, kbytes) || overlaps(workspace, L.total, keys_in, kbytes))
+        return FS_ERR_INVALID_ARG;
+
+    char* w = static_cast<char*>(workspace);
+    uint32_t* err = reinterpret_cast<uint32_t*>(w + L.err);
+    uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
+    uint32_t* plan = reinterpret_cast<uint32_t*>(w + L.plan);
+    uint64_t* hist = reinterpret_cast<uint64_t*>(w + L.hist);
+    uint64_t* base = reinterpret_cast<uint64_t*>(w + L.base);
+    uint32_t* part = reinterpret_cast<uint32_t*>(w + L.part);
+
+    FS_TRY(launch_fill_u32(err, 1 + 8ull * L.portions, 0, s));
+
+    if (L.compressed16) {
+        uint32_t* wrap = reinterpret_cast<uint32_t*>(w + L.wrap);
+        uint64_t* h16 = reinterpret_cast<uint64_t*>(w + L.h16);
+        FS_TRY(launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
+        FS_TRY(launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups, part, wrap,
+                              wrap + kHist16Words, s));
+        FS_TRY(launch_merge16(part, L.hist_groups, wrap, wrap + kHist16Words, h16, s));
+        if (L.expand16) {
+            uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
+            FS_TRY(launch_scan16(h16, p16, s));
+            FS_TRY(launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
+            return FS_OK;
+        }
+        FS_TRY(launch_plan_from16(h16, n, hist, base, plan, s));
+    } else {
+        FS_TRY(launch_hist8(keys_in, n, kb, L.hist_groups, part, s));
+        FS_TRY(launch_plan8(part, L.hist_groups, L.digits, n, hist, base, plan, s));
+    }
+
+    uint32_t* state = reinterpret_cast<uint32_t*>(w + L.state);
+    const uint64_t T = scatter_shape(kb, val_bytes).tile();
+    for (int j = 0; j < L.digits; ++j) {
+        for (uint32_t q = 0; q < L.portions; ++q) {
+            const uint64_t pb = (uint64_t)q * kPortionKeys;
+            const uint64_t plen = std::min<uint64_t>(kPortionKeys, n - pb);
+            const uint32_t tiles = (uint32_t)ceil_div(plen, T);
+            FS_TRY(launch_fill_u32(state, (uint64_t)tiles * kRadix, 0, s));
+            ScatterArgs a;
+            a.in_k = keys_in;
+            a.out_k = keys_out;
+            a.tmp_k = w + L.tmp_keys;
+            a.in_v = vals_in;
+            a.out_v = vals_out;
+            a.tmp_v = val_bytes ? w + L.tmp_vals : nullptr;
+            a.n = n;
+            a.portion_begin = pb;
+            a.portion_len = plen;
+            a.tiles = tiles;
+            a.shift = 8 * j;
+            a.pass = j;
+            a.plan = plan;
+            a.base_cur = base + (uint64_t)j * 2 * kRadix + (q % 2) * kRadix;
+            a.base_next = base + (uint64_t)j * 2 * kRadix + ((q + 1) % 2) * kRadix;
+            a.state = state;
+            a.ticket = tickets + j * L.portions + q;
+            a.err = err;
+            FS_TRY(launch_scatter(a, kb, val_bytes, s));
+        }
+    }
+    FS_TRY(launch_copy_if(plan, keys_in, keys_out, kbytes, s));
+    if (val_bytes) FS_TRY(launch_copy_if(plan, vals_in, vals_out, vbytes, s));
+    return FS_OK;
+}
+
+}  // namespace fs
+
+extern "C" {
+
+fs_status fs_sort_keys(const void* keys_in, void* keys_out, uint64_t n, int key_bits, unsigned flags,
+                       void* workspace, size_t* workspace_bytes, void* stream) {
+    if (flags != FS_FLAG_NONE) return FS_ERR_INVALID_ARG;
+    return fs::sort_impl(keys_in, keys_out, nullptr, nullptr, n, key_bits, 0, workspace,
+                         workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+fs_status fs_sort_pairs(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                        uint64_t n, int key_bits, int val_bytes, unsigned flags, void* workspace,
+                        size_t* workspace_bytes, void* stream) {
+    if (flags != FS_FLAG_NONE) return FS_ERR_INVALID_ARG;
+    if (val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
+    return fs::sort_impl(keys_in, keys_out, vals_in, vals_out, n, key_bits, val_bytes, workspace,
+                         workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+fs_status fs_digit_histograms(const void* keys, uint64_t n, int key_bits, int digit_bits,
+                              uint64_t* hist_out, void* workspace, size_t* workspace_bytes,
+                              void* stream) {
+    using namespace fs;
+    if (key_bits != 16 && key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
+    if (digit_bits != 8 && !(digit_bits == 16 && key_bits == 16)) return FS_ERR_INVALID_ARG;
+    if (!workspace_bytes || n > kMaxKeys) return FS_ERR_INVALID_ARG;
+    const int kb = key_bits / 8;
+    const int cus = device_cu_count();
+    uint32_t groups;
+    size_t need;
+    if (digit_bits == 16) {
+        groups = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), cus);
+        need = align_up(4ull * groups * kHist16Words, 256) + 4ull * 2 * kHist16Words;
+    } else {
+        groups = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, (uint64_t)kHist8Threads * 16), 1),
+                                              2ull * cus);
+        need = 4ull * groups * kb * kRadix;
+    }
+    need = align_up(need, 256);
+    if (!workspace) {
+        *workspace_bytes = need;
+        return FS_OK;
+    }
+    if (*workspace_bytes < need) return FS_ERR_WORKSPACE_TOO_SMALL;
+    if (!hist_out || (n && !keys) || !aligned(workspace, 256) || !aligned(hist_out, 8) ||
+        (keys && !aligned(keys, kb)))
+        return FS_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t* part = static_cast<uint32_t*>(workspace);
+    if (digit_bits == 16) {
+        uint32_t* wrap = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) +
+                                                     align_up(4ull * groups * kHist16Words, 256));
+        FS_TRY(launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
+        if (n) FS_TRY(launch_hist16c(static_cast<const uint16_t*>(keys), n, groups, part, wrap, wrap + kHist16Words, s));
+        else FS_TRY(launch_fill_u32(part, kHist16Words, 0, s));
+        FS_TRY(launch_merge16(part, n ? groups : 1, wrap, wrap + kHist16Words, hist_out, s));
+    } else {
+        if (n) FS_TRY(launch_hist8(keys, n, kb, groups, part, s));
+        else FS_TRY(launch_fill_u32(part, (uint64_t)kb * kRadix, 0, s));
+        FS_TRY(launch_reduce8(part, n ? groups : 1, kb, hist_out, s));
+    }
+    return FS_OK;
+}
+
+fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments, uint64_t total_keys,
+                            uint64_t max_segment_keys, unsigned flags, void* workspace,
+                            size_t* workspace_bytes, void* stream) {
+    (void)d_segments; (void)num_segments; (void)total_keys; (void)max_segment_keys;
+    (void)flags; (void)workspace; (void)workspace_bytes; (void)stream;
+    return FS_ERR_UNSUPPORTED;
+}
+
+const char* fs_status_string(fs_status s) {
+    switch (s) {
+    case FS_OK: return "FS_OK";
+    case FS_ERR_INVALID_ARG: return "FS_ERR_INVALID_ARG";
+    case FS_ERR_UNSUPPORTED: return "FS_ERR_UNSUPPORTED";
+    case FS_ERR_WORKSPACE_TOO_SMALL: return "FS_ERR_WORKSPACE_TOO_SMALL";
+    case FS_ERR_DEVICE: return "FS_ERR_DEVICE";
+    default: return "FS_ERR_UNKNOWN";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Device-side helpers shared by the sort kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fs {
+
+constexpr int kWave = 64;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Look-back state word: 2-bit flag over a 30-bit count (counts within one
+// portion stay below 2^30, see kPortionKeys).
+constexpr uint32_t kFlagAggregate = 1u << 30;
+constexpr uint32_t kFlagPrefix = 2u << 30;
+constexpr uint32_t kCountMask = (1u << 30) - 1;
+
+// Bound on look-back polls before a workgroup gives up and raises the
+// workspace error word (never reached by a correct launch; it keeps every
+// wave finite).
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+// Plan words written by the planning kernel and read by every pass kernel.
+// pass j: plan[4j] = active, plan[4j+1] = source buffer, plan[4j+2] = dest.
+// plan[kPlanCopy] = 1 when no pass is active and the input must be copied.
+constexpr int kPlanCopy = 64;
+constexpr int kPlanWords = 68;
+enum BufSel : uint32_t { kBufIn = 0, kBufOut = 1, kBufTmp = 2 };
+
+struct NoVal {};
+
+// 16-byte vector usable with the non-temporal load/store builtins
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// number of set bits of m in lanes below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__builtin_popcountll(m); }
+
+// Lanes of `candidates` whose 8-bit digit equals this lane's digit: one
+// ballot per digit bit, each keeping the lanes that agree on that bit.
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t candidates) {
+    uint64_t peers = candidates;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_agent(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
+    return (uint32_t)((uint64_t)key >> shift) & (kRadix - 1);
+}
+
+// Exclusive scan of one value per thread over the first 256 threads of a
+// block (4 waves); every thread of the block must call it.  `wsum` is LDS
+// scratch of at least 4 words.  Returns the exclusive prefix for threads
+// < 256 and the total in *total (all threads).
+template <typename T>
+__device__ __forceinline__ T scan256_exclusive(T x, T* wsum, T* total) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (wave < 4 && lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        T s = wsum[w];
+        if (w < wave) before += s;
+        all += s;
+    }
+    *total = all;
+    __syncthreads();
+    return before + inc - x;
+}
+
+}  // namespace fs

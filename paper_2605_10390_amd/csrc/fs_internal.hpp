@@ -1,0 +1,86 @@
+// Host-side internals: workspace layout and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fs {
+
+// Keys per look-back portion of one pass.  Counts inside a portion stay
+// below 2^30, so a look-back state word holds flag + count in 32 bits;
+// portions of a pass run as consecutive launches and hand their running bin
+// bases on through the workspace.
+constexpr uint64_t kPortionKeys = 1ull << 28;
+
+// Histogram launch shapes.
+constexpr int kHist16Threads = 1024;
+constexpr int kHist16Words = 32768;  // 2^16 bins as packed 16-bit counter pairs
+constexpr int kHist8Threads = 512;
+
+struct ScatterShape {
+    int threads;
+    int items;
+    int tile() const { return threads * items; }
+};
+
+// Tile shape of the scatter pass for a key/value width.
+ScatterShape scatter_shape(int key_bytes, int val_bytes);
+
+// Offsets (bytes) of every region of a sort's workspace.
+struct SortLayout {
+    int key_bytes = 0, val_bytes = 0, digits = 0;
+    bool expand16 = false;    // 16-bit keys only: histogram + expansion
+    bool compressed16 = false;  // digit histograms from the compressed 2^16-bin histogram
+    uint32_t hist_groups = 0;   // workgroups of the histogram kernel
+    uint32_t portions = 0, tiles_per_portion = 0;
+    size_t err = 0, tickets = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0,
+           p16 = 0, state = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
+};
+
+SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus);
+int device_cu_count();
+
+// ---- launchers (each returns hipGetLastError after enqueueing) ----------
+hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStream_t s);
+
+hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uint32_t* part,
+                          uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s);
+hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t* wrap_lo,
+                          const uint32_t* wrap_word, uint64_t* h16, hipStream_t s);
+hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s);
+hipError_t launch_plan_from16(const uint64_t* h16, uint64_t n, uint64_t* hist, uint64_t* base,
+                              uint32_t* plan, hipStream_t s);
+hipError_t launch_hist8(const void* keys, uint64_t n, int key_bytes, uint32_t groups,
+                        uint32_t* part, hipStream_t s);
+hipError_t launch_plan8(const uint32_t* part, uint32_t groups, int digits, uint64_t n,
+                        uint64_t* hist, uint64_t* base, uint32_t* plan, hipStream_t s);
+hipError_t launch_reduce8(const uint32_t* part, uint32_t groups, int digits, uint64_t* hist,
+                          hipStream_t s);
+hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t n, hipStream_t s);
+hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
+                          hipStream_t s);
+
+struct ScatterArgs {
+    const void* in_k;
+    void* out_k;
+    void* tmp_k;
+    const void* in_v;
+    void* out_v;
+    void* tmp_v;
+    uint64_t n;  // total keys (bound of every destination index)
+    uint64_t portion_begin;
+    uint64_t portion_len;
+    uint32_t tiles;
+    int shift;
+    int pass;
+    const uint32_t* plan;
+    const uint64_t* base_cur;
+    uint64_t* base_next;
+    uint32_t* state;
+    uint32_t* ticket;
+    uint32_t* err;
+};
+
+hipError_t launch_scatter(const ScatterArgs& a, int key_bytes, int val_bytes, hipStream_t s);
+
+}  // namespace fs

@@ -1,0 +1,445 @@
+// Histogram, merge, prefix-scan, plan and expansion kernels.
+//
+// The histogram follows the paper's compressed tree of counters (Section
+// III-B.1 Fractal RMW, Algorithm 1; counter width tapering, Section
+// III-D.1).  For a d-bit digit the tree is complete and implicit (Algorithm
+// 4: nodes at computable positions, no pointers), its leaves are the 2^d
+// digit values and every inner node is the sum of its leaves, so a key
+// updates only its leaf and the inner sums are produced by the prefix scan.
+// The leaf counters are narrow: the 2^16-bin histogram of 16-bit keys keeps
+// two 16-bit counters per 32-bit LDS word (128 KiB, which fits the 160 KiB
+// LDS of a CDNA4 compute unit where 2^16 32-bit counters would not), and a
+// counter that wraps is repaired exactly from side counts kept in global
+// memory (see k_hist16c).
+#include "fs_device.hpp"
+#include "fs_internal.hpp"
+
+namespace fs {
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t words, uint32_t value) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+        p[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    uint64_t g = (words + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_fill_u32<<<(unsigned)g, 256, 0, s>>>(p, words, value);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Compressed 2^16-bin histogram of 16-bit keys, one per workgroup.
+//
+// Counter pair w holds bin 2w in its low half and bin 2w+1 in its high half.
+// Every increment is a returning LDS add, so the adding lane sees the old
+// word and can tell whether its add carried out of the low half (which also
+// bumped the high half by one) or out of the whole word.  Atomic adds are
+// linearised, so each wrap is seen by exactly one lane, which counts it in
+// wrap_lo[w] or wrap_word[w] (global, rare: one per 65536 keys of a bin).
+// Exact decode of the sums over all workgroups, with W_i the raw words:
+//   lo  = sum(W_i & 0xFFFF) + 2^16 * wrap_lo[w]
+//   V   = sum(W_i)          + 2^32 * wrap_word[w]     (= lo + 2^16 * hi)
+//   hi  = (V - lo) / 2^16
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void hist16_add(uint32_t* cnt, uint32_t key, uint32_t c,
+                                           uint32_t* wrap_lo, uint32_t* wrap_word) {
+    const uint32_t w = key >> 1;
+    const uint32_t inc = (key & 1u) ? (c << 16) : c;
+    const uint32_t old = atomicAdd(&cnt[w], inc);
+    const bool word_wrap = (old + inc) < old;
+    const bool lo_wrap = ((old & 0xFFFFu) + (inc & 0xFFFFu)) > 0xFFFFu;
+    if (__builtin_expect(word_wrap, 0)) atomicAdd(&wrap_word[w], 1u);
+    if (__builtin_expect(lo_wrap, 0)) atomicAdd(&wrap_lo[w], 1u);
+}
+
+__global__ __launch_bounds__(kHist16Threads) void k_hist16c(
+    const uint16_t* __restrict__ keys, uint64_t n, uint64_t head, uint64_t nvec,
+    uint32_t* __restrict__ part, uint32_t* wrap_lo, uint32_t* wrap_word) {
+    __shared__ uint32_t cnt[kHist16Words];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHist16Words; i += kHist16Threads) cnt[i] = 0;
+    __syncthreads();
+
+    // contiguous chunk of 8-key vectors for this workgroup
+    const uint64_t per = (nvec + gridDim.x - 1) / gridDim.x;
+    const uint64_t v0 = (uint64_t)blockIdx.x * per;
+    const uint64_t v1 = v0 + per < nvec ? v0 + per : nvec;
+    const u32x4* vec = reinterpret_cast<const u32x4*>(keys + head);
+    for (uint64_t v = v0 + tid; v < v1; v += kHist16Threads) {
+        const u32x4 q = __builtin_nontemporal_load(&vec[v]);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        // whole wave holding one key value: one add for all of it
+        const uint32_t k0 = w[0] & 0xFFFFu;
+        const bool uniform_lane = (w[0] >> 16) == k0 && w[1] == w[0] && w[2] == w[0] && w[3] == w[0];
+        const uint32_t kw = __builtin_amdgcn_readfirstlane(k0);
+        const uint64_t active = ballot(true);
+        const uint64_t same = ballot(uniform_lane && k0 == kw);
+        if (same == active) {
+            if (lanes_below(active) == 0)
+                hist16_add(cnt, kw, 8u * popc64(active), wrap_lo, wrap_word);
+            continue;
+        }
+        // otherwise one add per run of equal keys within the lane
+        uint32_t k[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) k[e] = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+        uint32_t run = 1;
+#pragma unroll
+        for (int e = 0; e < 7; ++e) {
+            if (k[e + 1] == k[e]) {
+                ++run;
+            } else {
+                hist16_add(cnt, k[e], run, wrap_lo, wrap_word);
+                run = 1;
+            }
+        }
+        hist16_add(cnt, k[7], run, wrap_lo, wrap_word);
+    }
+    // the few keys before the first 16-byte boundary and after the last vector
+    if (blockIdx.x == 0) {
+        const uint64_t tail0 = head + 8 * nvec;
+        const uint64_t extra = head + (n - tail0);
+        for (uint64_t e = tid; e < extra; e += kHist16Threads) {
+            const uint64_t i = e < head ? e : tail0 + (e - head);
+            hist16_add(cnt, keys[i], 1u, wrap_lo, wrap_word);
+        }
+    }
+    __syncthreads();
+    uint32_t* dst = part + (uint64_t)blockIdx.x * kHist16Words;
+    for (int i = tid; i < kHist16Words; i += kHist16Threads) dst[i] = cnt[i];
+}
+
+hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uint32_t* part,
+                          uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(keys);
+    uint64_t head = ((16 - (a & 15)) & 15) / 2;
+    if (head > n) head = n;
+    const uint64_t nvec = (n - head) / 8;
+    k_hist16c<<<groups, kHist16Threads, 0, s>>>(keys, n, head, nvec, part, wrap_lo, wrap_word);
+    return hipGetLastError();
+}
+
+// Sum the per-workgroup packed counters and repair wraps -> exact uint64
+// counts of all 2^16 bins (the global merge of Section III-A.1 / III-B).
+__global__ __launch_bounds__(256) void k_merge16(const uint32_t* __restrict__ part, uint32_t groups,
+                                                 const uint32_t* __restrict__ wrap_lo,
+                                                 const uint32_t* __restrict__ wrap_word,
+                                                 uint64_t* __restrict__ h16) {
+    const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+    if (w >= (uint32_t)kHist16Words) return;
+    uint64_t lo = 0, all = 0;
+    for (uint32_t g = 0; g < groups; ++g) {
+        const uint32_t x = part[(uint64_t)g * kHist16Words + w];
+        lo += x & 0xFFFFu;
+        all += x;
+    }
+    lo += (uint64_t)wrap_lo[w] << 16;
+    all += (uint64_t)wrap_word[w] << 32;
+    h16[2 * w] = lo;
+    h16[2 * w + 1] = (all - lo) >> 16;
+}
+
+hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t* wrap_lo,
+                          const uint32_t* wrap_word, uint64_t* h16, hipStream_t s) {
+    k_merge16<<<kHist16Words / 256, 256, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
+    return hipGetLastError();
+}
+
+// Exclusive prefix of the 2^16 bins (GetIndex of every value, Algorithm 3):
+// p16[v] = sum(h16[0..v-1]), p16[65536] = n.  One block of 1024 threads,
+// 64 consecutive bins per thread.
+__global__ __launch_bounds__(1024) void k_scan16(const uint64_t* __restrict__ h16,
+                                                 uint64_t* __restrict__ p16) {
+    __shared__ uint64_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t* h = h16 + tid * 64;
+    uint64_t local = 0;
+    for (int i = 0; i < 64; ++i) local += h[i];
+    uint64_t inc = local;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    uint64_t run = before + inc - local;
+    for (int i = 0; i < 64; ++i) {
+        p16[tid * 64 + i] = run;
+        run += h[i];
+    }
+    if (tid == 0) p16[65536] = total;
+}
+
+hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s) {
+    k_scan16<<<1, 1024, 0, s>>>(h16, p16);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Plan: per digit, the exclusive prefix of its 256 bins (where each bin's
+// block starts in the pass output) and whether the digit is trivial (one
+// bin holds every key, so its stable scatter is the identity and the pass is
+// skipped).  Active passes ping-pong between the output and the temporary
+// buffer so that the last one lands in the output.  256 threads, thread b
+// owns bin b; h[j] is this thread's count of digit j.
+// ----------------------------------------------------------------------------
+__device__ void finish_plan(const uint64_t* h, int digits, uint64_t n, uint64_t* hist,
+                            uint64_t* base, uint32_t* plan) {
+    __shared__ uint64_t wsum[4];
+    __shared__ uint32_t trivial[8];
+    const int b = threadIdx.x;
+    for (int j = 0; j < digits; ++j) {
+        uint64_t total;
+        const uint64_t start = scan256_exclusive<uint64_t>(h[j], wsum, &total);
+        hist[j * kRadix + b] = h[j];
+        base[(uint64_t)j * 2 * kRadix + b] = start;  // buffer 0 of pass j
+        const int any = __syncthreads_or(h[j] == n);
+        if (b == 0) trivial[j] = any;
+    }
+    __syncthreads();
+    if (b == 0) {
+        int active_count = 0;
+        for (int j = 0; j < digits; ++j) active_count += trivial[j] ? 0 : 1;
+        int i = 0;
+        uint32_t prev = kBufIn;
+        for (int j = 0; j < 16; ++j) {
+            const bool act = j < digits && !trivial[j];
+            plan[4 * j] = act ? 1u : 0u;
+            plan[4 * j + 1] = 0;
+            plan[4 * j + 2] = 0;
+            plan[4 * j + 3] = 0;
+            if (act) {
+                const uint32_t dst = ((active_count - 1 - i) % 2 == 0) ? kBufOut : kBufTmp;
+                plan[4 * j + 1] = prev;
+                plan[4 * j + 2] = dst;
+                prev = dst;
+                ++i;
+            }
+        }
+        plan[kPlanCopy] = active_count == 0 ? 1u : 0u;
+    }
+}
+
+// Digit histograms of 16-bit keys as marginals of the 2^16-bin histogram:
+// digit 0 (low byte) sums each column, digit 1 (high byte) each row.
+__global__ __launch_bounds__(256) void k_plan_from16(const uint64_t* __restrict__ h16, uint64_t n,
+                                                     uint64_t* hist, uint64_t* base, uint32_t* plan) {
+    const int b = threadIdx.x;
+    uint64_t h[2] = {0, 0};
+    for (int i = 0; i < 256; ++i) {
+        h[0] += h16[i * 256 + b];
+        h[1] += h16[b * 256 + i];
+    }
+    finish_plan(h, 2, n, hist, base, plan);
+}
+
+hipError_t launch_plan_from16(const uint64_t* h16, uint64_t n, uint64_t* hist, uint64_t* base,
+                              uint32_t* plan, hipStream_t s) {
+    k_plan_from16<<<1, 256, 0, s>>>(h16, n, hist, base, plan);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Per-workgroup 8-bit digit histograms of all digits in one read of the keys.
+// part[g][j][b] = count of digit j == b among workgroup g's keys.
+// ----------------------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(kHist8Threads) void k_hist8(const K* __restrict__ keys, uint64_t n,
+                                                         uint64_t head, uint64_t nvec,
+                                                         uint32_t* __restrict__ part) {
+    constexpr int D = sizeof(K);
+    constexpr int VK = 16 / sizeof(K);
+    __shared__ uint32_t cnt[D][kRadix];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < D * kRadix; i += kHist8Threads) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t per = (nvec + gridDim.x - 1) / gridDim.x;
+    const uint64_t v0 = (uint64_t)blockIdx.x * per;
+    const uint64_t v1 = v0 + per < nvec ? v0 + per : nvec;
+    const u32x4* vec = reinterpret_cast<const u32x4*>(keys + head);
+    for (uint64_t v = v0 + tid; v < v1; v += kHist8Threads) {
+        const u32x4 q = __builtin_nontemporal_load(&vec[v]);
+        K k[VK];
+        __builtin_memcpy(k, &q, 16);
+        bool lane_same = true;
+#pragma unroll
+        for (int e = 1; e < VK; ++e) lane_same &= k[e] == k[0];
+        const uint64_t active = ballot(true);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)k[0]);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)k[0] >> 32));
+        const uint64_t kw = ((uint64_t)hi << 32) | lo;
+        if (ballot(lane_same && (uint64_t)k[0] == kw) == active) {
+            if (lanes_below(active) == 0) {
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    atomicAdd(&cnt[j][digit_of<uint64_t>(kw, 8 * j)], (uint32_t)VK * popc64(active));
+            }
+            continue;
+        }
+#pragma unroll
+        for (int e = 0; e < VK; ++e) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) atomicAdd(&cnt[j][digit_of<K>(k[e], 8 * j)], 1u);
+        }
+    }
+    if (blockIdx.x == 0) {
+        const uint64_t tail0 = head + (uint64_t)VK * nvec;
+        const uint64_t extra = head + (n - tail0);
+        for (uint64_t e = tid; e < extra; e += kHist8Threads) {
+            const K key = keys[e < head ? e : tail0 + (e - head)];
+#pragma unroll
+            for (int j = 0; j < D; ++j) atomicAdd(&cnt[j][digit_of<K>(key, 8 * j)], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* dst = part + (uint64_t)blockIdx.x * D * kRadix;
+    for (int i = tid; i < D * kRadix; i += kHist8Threads) dst[i] = (&cnt[0][0])[i];
+}
+
+hipError_t launch_hist8(const void* keys, uint64_t n, int key_bytes, uint32_t groups,
+                        uint32_t* part, hipStream_t s) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(keys);
+    uint64_t head = ((16 - (a & 15)) & 15) / key_bytes;
+    if (head > n) head = n;
+    const uint64_t nvec = (n - head) / (16 / key_bytes);
+    switch (key_bytes) {
+    case 2: k_hist8<uint16_t><<<groups, kHist8Threads, 0, s>>>((const uint16_t*)keys, n, head, nvec, part); break;
+    case 4: k_hist8<uint32_t><<<groups, kHist8Threads, 0, s>>>((const uint32_t*)keys, n, head, nvec, part); break;
+    default: k_hist8<uint64_t><<<groups, kHist8Threads, 0, s>>>((const uint64_t*)keys, n, head, nvec, part); break;
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_plan8(const uint32_t* __restrict__ part, uint32_t groups,
+                                               int digits, uint64_t n, uint64_t* hist,
+                                               uint64_t* base, uint32_t* plan) {
+    const int b = threadIdx.x;
+    uint64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t g = 0; g < groups; ++g) {
+        const uint32_t* p = part + (uint64_t)g * digits * kRadix;
+        for (int j = 0; j < digits; ++j) h[j] += p[j * kRadix + b];
+    }
+    finish_plan(h, digits, n, hist, base, plan);
+}
+
+hipError_t launch_plan8(const uint32_t* part, uint32_t groups, int digits, uint64_t n,
+                        uint64_t* hist, uint64_t* base, uint32_t* plan, hipStream_t s) {
+    k_plan8<<<1, 256, 0, s>>>(part, groups, digits, n, hist, base, plan);
+    return hipGetLastError();
+}
+
+// Sum per-workgroup digit histograms into uint64 counts (no plan).
+__global__ __launch_bounds__(256) void k_reduce8(const uint32_t* __restrict__ part, uint32_t groups,
+                                                 int digits, uint64_t* __restrict__ hist) {
+    const int j = blockIdx.x, b = threadIdx.x;
+    uint64_t h = 0;
+    for (uint32_t g = 0; g < groups; ++g) h += part[((uint64_t)g * digits + j) * kRadix + b];
+    hist[j * kRadix + b] = h;
+}
+
+hipError_t launch_reduce8(const uint32_t* part, uint32_t groups, int digits, uint64_t* hist,
+                          hipStream_t s) {
+    k_reduce8<<<digits, 256, 0, s>>>(part, groups, digits, hist);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Keys-only 16-bit sort written straight from the histogram (Algorithm 5
+// with no trailing bits): out[i] = v for p16[v] <= i < p16[v+1].  Each
+// workgroup owns 8192 output slots; it finds the value at its first and last
+// slot by an order-statistic search of the prefix (GetItem, Algorithm 2),
+// then every thread writes 8 consecutive keys with one 16-byte store.
+// ----------------------------------------------------------------------------
+constexpr int kExpandThreads = 256;
+constexpr int kExpandGroupsPerThread = 4;
+constexpr int kExpandSpan = kExpandThreads * 8 * kExpandGroupsPerThread;
+
+// largest v in [lo, hi] with p[v] <= pos (p non-decreasing, p[lo] <= pos)
+__device__ __forceinline__ uint32_t value_at(const uint64_t* p, uint32_t lo, uint32_t hi, uint64_t pos) {
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (p[mid] <= pos) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool kVec>
+__global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __restrict__ p16,
+                                                             uint16_t* __restrict__ out, uint64_t n) {
+    __shared__ uint32_t window[2];
+    const uint64_t rs = (uint64_t)blockIdx.x * kExpandSpan;
+    const uint64_t re = rs + kExpandSpan < n ? rs + kExpandSpan : n;
+    if (threadIdx.x == 0) {
+        window[0] = value_at(p16, 0, 65535, rs);
+        window[1] = value_at(p16, 0, 65535, re - 1);
+    }
+    __syncthreads();
+    const uint32_t vlo = window[0], vhi = window[1];
+#pragma unroll
+    for (int u = 0; u < kExpandGroupsPerThread; ++u) {
+        const uint64_t p0 = rs + ((uint64_t)u * kExpandThreads + threadIdx.x) * 8;
+        if (p0 >= re) break;
+        uint32_t v = value_at(p16, vlo, vhi, p0);
+        uint64_t next = p16[v + 1];
+        uint32_t o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint64_t pos = p0 + e < n ? p0 + e : n - 1;
+            while (next <= pos) {  // p16[65536] = n > pos, so v stays <= 65535
+                ++v;
+                next = p16[v + 1];
+            }
+            o[e] = v;
+        }
+        if (kVec && p0 + 8 <= n) {
+            u32x4 q;
+            q.x = o[0] | (o[1] << 16);
+            q.y = o[2] | (o[3] << 16);
+            q.z = o[4] | (o[5] << 16);
+            q.w = o[6] | (o[7] << 16);
+            __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out + p0));
+        } else {
+            for (int e = 0; e < 8 && p0 + e < n; ++e) out[p0 + e] = (uint16_t)o[e];
+        }
+    }
+}
+
+hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t n, hipStream_t s) {
+    const uint64_t groups = (n + kExpandSpan - 1) / kExpandSpan;
+    const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    if (vec) k_expand16<true><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, n);
+    else k_expand16<false><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, n);
+    return hipGetLastError();
+}
+
+// Copy src -> dst when the plan found every digit trivial (the sorted
+// result is then the input itself).
+template <typename W>
+__global__ void k_copy_if(const uint32_t* plan, const W* __restrict__ src, W* __restrict__ dst,
+                          uint64_t words) {
+    if (!plan[kPlanCopy]) return;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
+                          hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const uintptr_t m = reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes;
+    auto grid = [](uint64_t words) { uint64_t g = (words + 255) / 256; return (unsigned)(g > 8192 ? 8192 : g); };
+    if ((m & 15) == 0) k_copy_if<uint4><<<grid(bytes / 16), 256, 0, s>>>(plan, (const uint4*)src, (uint4*)dst, bytes / 16);
+    else if ((m & 3) == 0) k_copy_if<uint32_t><<<grid(bytes / 4), 256, 0, s>>>(plan, (const uint32_t*)src, (uint32_t*)dst, bytes / 4);
+    else k_copy_if<uint16_t><<<grid(bytes / 2), 256, 0, s>>>(plan, (const uint16_t*)src, (uint16_t*)dst, bytes / 2);
+    return hipGetLastError();
+}
+
+}  // namespace fs

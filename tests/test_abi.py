@@ -1,0 +1,47 @@
+"""The C-ABI library loads and exports every symbol include/fs_sort.h
+declares (no GPU needed: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fs_sort.h")
+LIB = os.path.join(ROOT, "paper_2605_10390_amd", "libfsort.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("fs_sort_keys", "fs_sort_pairs", "fs_sort_segmented", "fs_digit_histograms",
+              "fs_status_string"):
+        assert s in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfsort.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for s in declared_symbols():
+        assert hasattr(lib, s), f"{s} not exported"
+    lib.fs_status_string.restype = ctypes.c_char_p
+    assert lib.fs_status_string(0) == b"FS_OK"
+    assert lib.fs_status_string(3) == b"FS_ERR_WORKSPACE_TOO_SMALL"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfsort.so not built")
+def test_argument_errors_need_no_gpu():
+    """Invalid widths are rejected before any device call."""
+    lib = ctypes.CDLL(LIB)
+    size = ctypes.c_size_t(0)
+    lib.fs_sort_keys.restype = ctypes.c_int
+    lib.fs_sort_keys.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_uint, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
+    assert lib.fs_sort_keys(None, None, 10, 24, 0, None, ctypes.byref(size), None) == 1
+    assert lib.fs_sort_keys(None, None, 10, 16, 7, None, ctypes.byref(size), None) == 1

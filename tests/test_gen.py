@@ -52,3 +52,15 @@ def test_distribution_shapes():
     hot = set(int(x) for x in fsgen.hot_table(6, 64))
     frac = np.mean(np.isin(h, np.array(sorted(hot), dtype=np.uint64)))
     assert abs(frac - 0.9) < 0.01
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bits", [16, 32, 64])
+def test_device_generator_matches_host(gpu, bits):
+    n = 100003
+    for di, dist in enumerate(fsgen.valid_dists(bits)):
+        seed = fsgen.seed_for(3, di)
+        d = fsgen.keys_device(dist, bits, n, seed).cpu().numpy()
+        h = fsgen.keys_host(dist, bits, n, seed)
+        assert np.array_equal(d, h), dist
+    assert np.array_equal(fsgen.index_device(n, 4).cpu().numpy(), np.arange(n, dtype=np.uint32))

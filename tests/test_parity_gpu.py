@@ -1,0 +1,166 @@
+"""GPU parity: every result of the HIP path equals the CPU oracle's, byte
+for byte (integer work: bit-exact, tolerance 0), on the same seeded inputs.
+
+Sizes span several tiles (a scatter tile is 4096 keys) with ragged tails,
+every key width and payload width, every distribution of the configs, and
+the edge cases: n = 0 and 1, unaligned buffers, all-equal keys (every digit
+trivial, the sort is a copy) and a size that crosses a look-back portion.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fsgen
+import oracle
+import paper_2605_10390_amd as fs
+from tests.checks import check_index_pairs
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 63, 64, 65, 4095, 4096, 4097, 3 * 4096 + 17, 65536 + 123, (1 << 20) + 7]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def _vals(n, vb, seed):
+    return fsgen.vals_host(n, vb, kind="random", seed=seed)
+
+
+@pytest.mark.parametrize("bits", [16, 32, 64])
+def test_keys_match_oracle(gpu, bits):
+    ws = fs.Workspace(gpu)
+    for n in SIZES:
+        for di, dist in enumerate(fsgen.valid_dists(bits)):
+            seed = fsgen.seed_for(9, di) + n
+            k = fsgen.keys_host(dist, bits, n, seed)
+            out = fs.sort_keys(dev(k), workspace=ws)
+            torch.cuda.synchronize()
+            assert ws.error_word() == 0
+            assert np.array_equal(host(out), oracle.sort(k)), (bits, n, dist)
+
+
+@pytest.mark.parametrize("bits", [16, 32, 64])
+@pytest.mark.parametrize("vb", [4, 8])
+def test_pairs_match_oracle(gpu, bits, vb):
+    ws = fs.Workspace(gpu)
+    for n in SIZES:
+        for di, dist in enumerate(fsgen.valid_dists(bits)):
+            seed = fsgen.seed_for(8, di) + n
+            k = fsgen.keys_host(dist, bits, n, seed)
+            v = _vals(n, vb, seed)
+            ko, vo = fs.sort_pairs(dev(k), dev(v), workspace=ws)
+            ek, ev = oracle.sort(k, v)
+            assert ws.error_word() == 0
+            assert np.array_equal(host(ko), ek), (bits, vb, n, dist)
+            assert np.array_equal(host(vo), ev), (bits, vb, n, dist)
+
+
+def test_index_payload_is_stable_permutation(gpu):
+    """The configs' payload (original index): invariants pin the result."""
+    n = 5 * 4096 + 3
+    for dist in fsgen.DISTS_16:
+        k = fsgen.keys_host(dist, 16, n, 11)
+        ko, vo = fs.sort_pairs(dev(k), dev(fsgen.vals_host(n, 4)))
+        check_index_pairs(k, host(ko), host(vo))
+
+
+def test_empty_and_single(gpu):
+    for bits in (16, 32, 64):
+        dt = fsgen.key_dtype(bits)
+        e = fs.sort_keys(dev(np.zeros(0, dtype=dt)))
+        assert e.numel() == 0
+        one = fs.sort_keys(dev(np.array([7], dtype=dt)))
+        assert host(one).tolist() == [7]
+        ko, vo = fs.sort_pairs(dev(np.array([9], dtype=dt)), dev(np.array([3], dtype=np.uint32)))
+        assert host(ko).tolist() == [9] and host(vo).tolist() == [3]
+
+
+def test_unaligned_buffers(gpu):
+    """Views that start 2 bytes past a 16-byte boundary exercise the
+    unaligned head and tail paths of the vector loads and stores."""
+    n = 70001
+    for bits in (16, 32, 64):
+        k = fsgen.keys_host("uniform", bits, n + 3, 5)
+        kd = dev(k)[1:1 + n]
+        outbuf = torch.empty(n + 1, dtype=kd.dtype, device=gpu)
+        out = fs.sort_keys(kd, out=outbuf[1:])
+        assert np.array_equal(host(out), oracle.sort(k[1:1 + n])), bits
+
+
+def test_all_equal_is_a_copy(gpu):
+    n = 3 * 4096 + 5
+    for bits in (16, 32, 64):
+        k = np.full(n, 12345, dtype=fsgen.key_dtype(bits))
+        v = np.arange(n, dtype=np.uint64)
+        ko, vo = fs.sort_pairs(dev(k), dev(v))
+        assert np.array_equal(host(ko), k) and np.array_equal(host(vo), v)
+
+
+def test_digit_histograms_match_oracle(gpu):
+    for bits in (16, 32, 64):
+        for dist in fsgen.valid_dists(bits):
+            for n in (1, 4097, (1 << 20) + 9):
+                k = fsgen.keys_host(dist, bits, n, 3)
+                h = host(fs.digit_histograms(dev(k), 8)).astype(np.uint64)
+                for j in range(bits // 8):
+                    assert np.array_equal(h[j], oracle.histogram(k, 8 * j, 8)), (bits, dist, n, j)
+    for dist in fsgen.DISTS_16:
+        for n in (1, 4097, (1 << 21) + 9):
+            k = fsgen.keys_host(dist, 16, n, 4)
+            h = host(fs.digit_histograms(dev(k), 16)).astype(np.uint64)[0]
+            assert np.array_equal(h, oracle.histogram(k, 0, 16)), (dist, n)
+
+
+def test_compressed_counters_wrap_exactly(gpu):
+    """All keys in one bin, and two bins sharing a counter word, each far
+    past 2^16 per workgroup and past 2^32 in total pairs of words: the
+    packed 16-bit counters wrap many times and must still decode exactly."""
+    n = (1 << 24) + 5
+    a = np.full(n, 0x1234, dtype=np.uint16)
+    h = host(fs.digit_histograms(dev(a), 16)).astype(np.uint64)[0]
+    assert h[0x1234] == n and h.sum() == n
+    b = np.where(np.arange(n) % 3 == 0, 0x4444, 0x4445).astype(np.uint16)
+    h = host(fs.digit_histograms(dev(b), 16)).astype(np.uint64)[0]
+    assert np.array_equal(h, oracle.histogram(b, 0, 16))
+    out = fs.sort_keys(dev(b))
+    assert np.array_equal(host(out), np.sort(b))
+
+
+def test_repeatable(gpu):
+    n = (1 << 20) + 11
+    k = dev(fsgen.keys_host("uniform", 32, n, 21))
+    v = dev(fsgen.vals_host(n, 4))
+    a = fs.sort_pairs(k, v)
+    b = fs.sort_pairs(k, v)
+    assert torch.equal(a[0].view(torch.int32), b[0].view(torch.int32))
+    assert torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+
+
+def test_invalid_arguments(gpu):
+    k = dev(np.arange(100, dtype=np.uint32))
+    with pytest.raises(fs.FsError) as e:
+        fs.sort_keys(k, out=k)  # in place is an overlap
+    assert e.value.status == fs.FS_ERR_INVALID_ARG
+    v = dev(np.arange(100, dtype=np.uint32))
+    with pytest.raises(fs.FsError):
+        fs.sort_pairs(k, v, vals_out=v)
+
+
+def test_crosses_a_lookback_portion(gpu):
+    """n just above one look-back portion (2^28 keys): the second portion
+    starts from the running bin bases handed over by the first."""
+    n = (1 << 28) + 4097
+    seed = fsgen.seed_for(1, 0)
+    kd = fsgen.keys_device("uniform", 16, n, seed)
+    vd = fsgen.index_device(n, 4)
+    ko, vo = fs.sort_pairs(kd, vd)
+    k = host(kd)
+    ek, ev = oracle.sort(k, np.arange(n, dtype=np.uint32))
+    assert np.array_equal(host(ko), ek)
+    assert np.array_equal(host(vo), ev)
