@@ -1,0 +1,240 @@
+"""Benchmark: Gkeys/s and fraction of the HBM roofline on one MI355X.
+
+Default workload: 2^31 uint16 keys (4 GiB) with a uint32 payload equal to
+the original index, keys i.i.d. uniform from the seeded generator; one
+"step" is one complete stable sort of that batch (compressed histogram,
+prefix scans and plan, two 8-bit scatter passes).  Inputs are resident in
+HBM before timing starts.
+
+Prints ONE JSON line.  Besides the contract fields it carries
+  roofline      -- the dominant kernel (the scatter pass): algorithmic bytes
+                   per launch / its average event-timed launch duration,
+                   against the 8 TB/s HBM peak; `traffic` from the committed
+                   rocprofv3 counter summary when it still matches the kernel
+                   source, else null;
+  cpu_baseline  -- the CPU oracle (single thread) on a bounded sample of the
+                   same workload, on this host;
+  kernels       -- per-kernel-kind launches, average ms and GB/s.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gkeys/s & % of HBM peak (16-bit, 4 GB); batched vs one-launch-per-sort"
+HBM_PEAK_GBPS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "scatter_u16u32_uniform_2e31_pmc.json")
+KERNEL_SOURCES = ["paper_2605_10390_amd/csrc/scatter.hip", "paper_2605_10390_amd/csrc/fs_device.hpp"]
+
+WORKLOADS = {
+    # name: (key_bits, val_bytes, log2 n, distribution, description)
+    "c1": (16, 4, 31, "uniform",
+           "key-value sort of 2^31 uint16 keys (4 GiB) + uint32 index payload, uniform"),
+    "c0": (16, 0, 28, "uniform", "keys-only sort of 2^28 uint16 keys (512 MiB), uniform"),
+    "c2a": (32, 4, 31, "uniform", "key-value sort of 2^31 uint32 keys (8 GiB) + uint32 index, uniform"),
+    "c2b": (64, 0, 32, "uniform", "keys-only sort of 2^32 uint64 keys (32 GiB), uniform"),
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def scatter_bytes_per_key(key_bits, val_bytes):
+    """Algorithmic bytes one scatter pass moves per key: read and write the
+    key and its payload once."""
+    return 2 * (key_bits // 8 + val_bytes)
+
+
+def algorithmic_bytes_per_key(key_bits, val_bytes, passes):
+    """Whole sort: one read of the keys for the histograms, then every pass
+    reads and writes key + payload; a 16-bit keys-only sort is one read plus
+    one write of the keys (expansion)."""
+    kb = key_bits // 8
+    if key_bits == 16 and val_bytes == 0:
+        return 2 * kb
+    return kb + passes * scatter_bytes_per_key(key_bits, val_bytes)
+
+
+def read_traffic(source_hash):
+    """HBM bytes per scatter launch from the committed counter summary, or
+    None when absent or taken on a different kernel source."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            s = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if s.get("kernel_source_sha256_16") != source_hash:
+        return None
+    return s.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(keys_dev, vals_dev, key_bits, val_bytes, budget_s=12.0):
+    """The oracle as it stands, single-threaded, on a bounded sample: the
+    first 2^26 keys (and payloads) of the same workload, repeated until about
+    `budget_s` seconds of CPU work."""
+    import numpy as np
+    import oracle
+    ns = min(1 << 26, keys_dev.numel())
+    k = keys_dev[:ns].cpu().numpy()
+    v = vals_dev[:ns].cpu().numpy() if vals_dev is not None else None
+    oracle.load()
+    reps, elapsed = 0, 0.0
+    while elapsed < budget_s or reps == 0:
+        t0 = time.perf_counter()
+        if v is None:
+            oracle.sort(k)
+        else:
+            oracle.sort(k, v)
+        elapsed += time.perf_counter() - t0
+        reps += 1
+    del np
+    return {"value": ns * reps / elapsed / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first 2^26 keys of the workload ({'keys only' if v is None else 'with payload'}),"
+                      f" sorted {reps}x single-threaded by the C oracle, {elapsed:.1f} s total"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design in DESIGN.md, not a measured path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import ctypes
+    import fsgen
+    import paper_2605_10390_amd as fs
+
+    key_bits, val_bytes, logn, dist, desc = WORKLOADS[args.workload]
+    n = 1 << logn
+    dev = torch.device("cuda:0")
+    seed = fsgen.seed_for({"c0": 0, "c1": 1, "c2a": 2, "c2b": 2}[args.workload], 0)
+    keys = fsgen.keys_device(dist, key_bits, n, seed, device=dev)
+    vals = fsgen.index_device(n, val_bytes, device=dev) if val_bytes else None
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(vals) if vals is not None else None
+    ws = fs.Workspace(dev)
+    if vals is None:
+        ws.get(fs.sort_keys_workspace_bytes(n, key_bits))
+    else:
+        ws.get(fs.sort_pairs_workspace_bytes(n, key_bits, val_bytes))
+    torch.cuda.synchronize()
+
+    def step():
+        if vals is None:
+            fs.sort_keys(keys, out=ko, workspace=ws)
+        else:
+            fs.sort_pairs(keys, vals, keys_out=ko, vals_out=vo, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps of {desc})", file=sys.stderr, flush=True)
+
+    L = fs.lib()
+    L.fs_profile_enable(1)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t0.elapsed_time(t1)
+    kinds = {"histogram": 0, "plan": 1, "scatter": 2, "expand": 3, "aux": 4}
+    kernels = {}
+    for name, kid in kinds.items():
+        c, k, ms = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+        L.fs_profile_read(kid, ctypes.byref(c), ctypes.byref(k), ctypes.byref(ms))
+        kernels[name] = {"launches": c.value, "keys": k.value, "ms_total": ms.value}
+    L.fs_profile_enable(0)
+    if ws.error_word() != 0:
+        raise SystemExit(f"device error word {ws.error_word():#x}: result invalid")
+
+    # cheap validity check of the last result (outside the timed region)
+    kk = ko.view(torch.int16).to(torch.int32) & 0xFFFF if key_bits == 16 else ko.view(
+        {32: torch.int32, 64: torch.int64}[key_bits])
+    if key_bits == 16:
+        assert bool((kk[1:] >= kk[:-1]).all()), "output keys not sorted"
+    print(f"[bench] timed {args.steps} steps in {ms_total:.1f} ms", file=sys.stderr, flush=True)
+
+    ms_step = ms_total / args.steps
+    gkeys = n * args.steps / (ms_total / 1e3) / 1e9
+    sc = kernels["scatter"]
+    passes = (sc["launches"] and round(sc["keys"] / args.steps / n)) or 0
+    bpk = algorithmic_bytes_per_key(key_bits, val_bytes, passes)
+    for name, kinfo in kernels.items():
+        if kinfo["launches"]:
+            kinfo["ms_avg"] = kinfo["ms_total"] / kinfo["launches"]
+            per_key = {"histogram": key_bits // 8, "scatter": scatter_bytes_per_key(key_bits, val_bytes),
+                       "expand": key_bits // 8}.get(name)
+            if per_key and kinfo["ms_total"] > 0:
+                kinfo["gbps"] = kinfo["keys"] * per_key / (kinfo["ms_total"] / 1e3) / 1e9
+    if key_bits == 16 and val_bytes == 0:
+        dom = kernels["expand"]
+        dom_bytes_per_key = 2  # the expansion writes every key once
+        dom_name = "k_expand16"
+    else:
+        dom = kernels["scatter"]
+        dom_bytes_per_key = scatter_bytes_per_key(key_bits, val_bytes)
+        dom_name = "k_scatter"
+    achieved = (dom["keys"] / dom["launches"]) * dom_bytes_per_key / (dom["ms_avg"] / 1e3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(src_hash) if dom_name == "k_scatter" and args.workload == "c1" else None
+    out = {
+        "metric": METRIC,
+        "value": round(gkeys, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {16: "u16", 32: "u32", 64: "u64"}[key_bits] + (f"+u{8 * val_bytes}" if val_bytes else ""),
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "key_bits": key_bits, "val_bytes": val_bytes,
+                   "distribution": dist, "seed": seed, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "bytes_per_key": dom_bytes_per_key,
+                     "keys_per_launch": dom["keys"] // max(dom["launches"], 1)},
+        "hbm_frac_whole_sort": round(n * bpk / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "algorithmic_bytes_per_key": bpk,
+        "kernels": {k: {kk2: (round(vv, 4) if isinstance(vv, float) else vv) for kk2, vv in v.items()}
+                    for k, v in kernels.items() if v["launches"]},
+        "kernel_source_sha256_16": src_hash,
+        "wall_s_timed": round(wall, 3),
+        "paper_context": "paper's CPU figure for 4 GB of 16-bit keys: 21.22 s on a 4-core i7-8665U "
+                         "(0.101 Gkeys/s); not this hardware, not a target",
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(keys, vals, key_bits, val_bytes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -52,6 +52,11 @@ def lib():
     L.fs_digit_histograms.restype = i32
     L.fs_sort_segmented.argtypes = [vp, u32, u64, u64, ctypes.c_uint, vp, sz, vp]
     L.fs_sort_segmented.restype = i32
+    L.fs_profile_enable.argtypes = [i32]
+    L.fs_profile_enable.restype = i32
+    L.fs_profile_read.argtypes = [i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.fs_profile_read.restype = i32
     L.fs_status_string.argtypes = [i32]
     L.fs_status_string.restype = ctypes.c_char_p
     _lib = L

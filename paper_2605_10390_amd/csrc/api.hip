@@ -1,6 +1,7 @@
 // C ABI entry points (include/fs_sort.h): argument checks, workspace layout
 // and the launch sequence of each call.  Host code only.
 #include "fs_sort.h"
+#include "fs_profile.h"
 #include "fs_device.hpp"
 #include "fs_internal.hpp"
 
@@ -54,7 +55,24 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
     } else {
         L.part = take(4ull * L.hist_groups * L.digits * kRadix);
     }
-    if (!L.expand16) {
+    L.chunked16 = key_bytes == 2 && val_bytes != 0 && n < (1ull << 32);
+    if (L.chunked16) {
+        static const int per_cu4 = range_scatter16_per_cu(4), per_cu8 = range_scatter16_per_cu(8);
+        const uint64_t resident = (uint64_t)num_cus * (val_bytes == 8 ? per_cu8 : per_cu4);
+        L.chunks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), resident);
+        L.ranges1 = L.chunks;
+        L.log_capacity = (uint32_t)(2 * (n >> 16) + 64);
+        L.J = take(4ull * L.chunks * 65536);
+        L.log = take(4ull + 4ull * L.log_capacity);
+        L.H = take(8ull * 65536);
+        L.RP = take(8ull * 65536);
+        L.O0 = take(8ull * (L.chunks + 1) * kRadix);
+        L.O1 = take(8ull * (L.ranges1 + 1) * kRadix);
+        L.start1 = take(8ull * (L.ranges1 + 1));
+        L.run1 = take(4ull * (L.ranges1 + 1));
+        L.tmp_keys = take((size_t)n * key_bytes);
+        L.tmp_vals = take((size_t)n * val_bytes);
+    } else if (!L.expand16) {
         L.state = take(4ull * kRadix * L.tiles_per_portion);
         L.tmp_keys = take((size_t)n * key_bytes);
         if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
@@ -76,6 +94,9 @@ constexpr uint64_t kMaxKeys = 1ull << 36;
     do {                                               \
         if ((expr) != hipSuccess) return FS_ERR_DEVICE; \
     } while (0)
+
+// enqueue `expr` (a launch) under the event recorder as kernel `kind`
+#define FS_LAUNCH(kind, keys, expr) FS_TRY(timed((kind), (keys), s, [&]() { return (expr); }))
 
 static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
                            uint64_t n, int key_bits, int val_bytes, void* workspace,
@@ -115,25 +136,69 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     uint64_t* base = reinterpret_cast<uint64_t*>(w + L.base);
     uint32_t* part = reinterpret_cast<uint32_t*>(w + L.part);
 
-    FS_TRY(launch_fill_u32(err, 1 + 8ull * L.portions, 0, s));
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(err, 1 + 8ull * L.portions, 0, s));
+
+    if (L.chunked16) {
+        Plan16 p;
+        p.chunks = L.chunks;
+        p.ranges1 = L.ranges1;
+        p.J = reinterpret_cast<uint32_t*>(w + L.J);
+        p.log_count = reinterpret_cast<uint32_t*>(w + L.log);
+        p.log_entries = p.log_count + 1;
+        p.log_capacity = L.log_capacity;
+        p.H = reinterpret_cast<uint64_t*>(w + L.H);
+        p.RP = reinterpret_cast<uint64_t*>(w + L.RP);
+        p.hist = hist;
+        p.base = base;
+        p.O0 = reinterpret_cast<uint64_t*>(w + L.O0);
+        p.O1 = reinterpret_cast<uint64_t*>(w + L.O1);
+        p.start1 = reinterpret_cast<uint64_t*>(w + L.start1);
+        p.run1 = reinterpret_cast<uint32_t*>(w + L.run1);
+        p.plan = plan;
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(p.log_count, 1, 0, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_joint16(keys_in, n, kb, 0, L.chunks, p.J, p.log_count,
+                                                         p.log_entries, p.log_capacity, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_chunked16(p, n, s));
+        for (int j = 0; j < 2; ++j) {
+            RangeArgs a;
+            a.in_k = keys_in;
+            a.out_k = keys_out;
+            a.tmp_k = w + L.tmp_keys;
+            a.in_v = vals_in;
+            a.out_v = vals_out;
+            a.tmp_v = w + L.tmp_vals;
+            a.n = n;
+            a.ranges = j == 0 ? L.chunks : L.ranges1;
+            a.range_start = j == 0 ? nullptr : p.start1;
+            a.offsets = j == 0 ? p.O0 : p.O1;
+            a.shift = 8 * j;
+            a.pass = j;
+            a.plan = plan;
+            a.err = err;
+            FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_range_scatter16(a, a.ranges, val_bytes, s));
+        }
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
+        return FS_OK;
+    }
 
     if (L.compressed16) {
         uint32_t* wrap = reinterpret_cast<uint32_t*>(w + L.wrap);
         uint64_t* h16 = reinterpret_cast<uint64_t*>(w + L.h16);
-        FS_TRY(launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
-        FS_TRY(launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups, part, wrap,
-                              wrap + kHist16Words, s));
-        FS_TRY(launch_merge16(part, L.hist_groups, wrap, wrap + kHist16Words, h16, s));
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups, part, wrap,
+                                                   wrap + kHist16Words, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part, L.hist_groups, wrap, wrap + kHist16Words, h16, s));
         if (L.expand16) {
             uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
-            FS_TRY(launch_scan16(h16, p16, s));
-            FS_TRY(launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
+            FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
+            FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
             return FS_OK;
         }
-        FS_TRY(launch_plan_from16(h16, n, hist, base, plan, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s));
     } else {
-        FS_TRY(launch_hist8(keys_in, n, kb, L.hist_groups, part, s));
-        FS_TRY(launch_plan8(part, L.hist_groups, L.digits, n, hist, base, plan, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist8(keys_in, n, kb, L.hist_groups, part, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan8(part, L.hist_groups, L.digits, n, hist, base, plan, s));
     }
 
     uint32_t* state = reinterpret_cast<uint32_t*>(w + L.state);
@@ -143,7 +208,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
             const uint64_t pb = (uint64_t)q * kPortionKeys;
             const uint64_t plen = std::min<uint64_t>(kPortionKeys, n - pb);
             const uint32_t tiles = (uint32_t)ceil_div(plen, T);
-            FS_TRY(launch_fill_u32(state, (uint64_t)tiles * kRadix, 0, s));
+            FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(state, (uint64_t)tiles * kRadix, 0, s));
             ScatterArgs a;
             a.in_k = keys_in;
             a.out_k = keys_out;
@@ -163,11 +228,11 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
             a.state = state;
             a.ticket = tickets + j * L.portions + q;
             a.err = err;
-            FS_TRY(launch_scatter(a, kb, val_bytes, s));
+            FS_LAUNCH(FS_KERNEL_SCATTER, plen, launch_scatter(a, kb, val_bytes, s));
         }
     }
-    FS_TRY(launch_copy_if(plan, keys_in, keys_out, kbytes, s));
-    if (val_bytes) FS_TRY(launch_copy_if(plan, vals_in, vals_out, vbytes, s));
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
+    if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
     return FS_OK;
 }
 

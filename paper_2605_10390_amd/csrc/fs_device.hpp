@@ -66,7 +66,11 @@ __device__ __forceinline__ uint32_t add_agent(uint32_t* p, uint32_t v) {
 
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
-    return (uint32_t)((uint64_t)key >> shift) & (kRadix - 1);
+    if constexpr (sizeof(K) <= 4)
+        return __builtin_amdgcn_ubfe((uint32_t)key, (uint32_t)shift, kRadixBits);
+    else
+        return shift < 32 ? __builtin_amdgcn_ubfe((uint32_t)key, (uint32_t)shift, kRadixBits)
+                          : __builtin_amdgcn_ubfe((uint32_t)(key >> 32), (uint32_t)(shift - 32), kRadixBits);
 }
 
 // Exclusive scan of one value per thread over the first 256 threads of a

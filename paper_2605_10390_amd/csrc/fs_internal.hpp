@@ -31,6 +31,9 @@ struct SortLayout {
     int key_bytes = 0, val_bytes = 0, digits = 0;
     bool expand16 = false;    // 16-bit keys only: histogram + expansion
     bool compressed16 = false;  // digit histograms from the compressed 2^16-bin histogram
+    bool chunked16 = false;     // 16-bit keys + payload: per-chunk histograms, no look-back
+    uint32_t chunks = 0, ranges1 = 0, log_capacity = 0;
+    size_t J = 0, log = 0, H = 0, RP = 0, O0 = 0, O1 = 0, start1 = 0, run1 = 0;
     uint32_t hist_groups = 0;   // workgroups of the histogram kernel
     uint32_t portions = 0, tiles_per_portion = 0;
     size_t err = 0, tickets = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0,
@@ -82,5 +85,56 @@ struct ScatterArgs {
 };
 
 hipError_t launch_scatter(const ScatterArgs& a, int key_bytes, int val_bytes, hipStream_t s);
+
+// ---- chunked two-pass path for 16-bit keys with payloads (chunked.hip) ----
+struct RangeArgs {
+    const void* in_k;
+    void* out_k;
+    void* tmp_k;
+    const void* in_v;
+    void* out_v;
+    void* tmp_v;
+    uint64_t n;
+    uint32_t ranges;              // number of workgroups / ranges
+    const uint64_t* range_start;  // ranges+1 starts, or null: equal chunks of n
+    const uint64_t* offsets;      // [ranges][256] first output position per digit value
+    int shift;
+    int pass;
+    const uint32_t* plan;
+    uint32_t* err;
+};
+
+struct Plan16 {
+    uint32_t chunks, ranges1;
+    uint32_t* J;  // [chunks][65536] per-chunk counts, then prefixes over chunks
+    uint32_t* log_count;
+    uint32_t* log_entries;
+    uint32_t log_capacity;
+    uint64_t *H, *RP, *hist, *base, *O0, *O1, *start1;
+    uint32_t* run1;
+    uint32_t* plan;
+};
+
+uint64_t chunk_begin(uint64_t n, uint32_t chunks, uint32_t c);
+hipError_t launch_joint16(const void* keys, uint64_t n, int key_bytes, int shift, uint32_t chunks,
+                          uint32_t* J, uint32_t* log_count, uint32_t* log_entries, uint32_t capacity,
+                          hipStream_t s);
+hipError_t launch_plan_chunked16(const Plan16& p, uint64_t n, hipStream_t s);
+hipError_t launch_range_scatter16(const RangeArgs& a, uint32_t groups, int val_bytes, hipStream_t s);
+int range_scatter16_per_cu(int val_bytes);  // resident workgroups per CU
+
+// ---- per-kernel event timing (include/fs_profile.h) ------------------------
+void profile_mark(int kind, uint64_t keys, hipStream_t s, hipEvent_t* begin_out);
+void profile_close(int kind, uint64_t keys, hipStream_t s, hipEvent_t begin);
+
+// Enqueue one launch, bracketed by timing events while profiling is on.
+template <typename F>
+hipError_t timed(int kind, uint64_t keys, hipStream_t s, F&& launch) {
+    hipEvent_t b = nullptr;
+    profile_mark(kind, keys, s, &b);
+    const hipError_t r = launch();
+    profile_close(kind, keys, s, b);
+    return r;
+}
 
 }  // namespace fs

@@ -13,6 +13,7 @@
 // memory (see k_hist16c).
 #include "fs_device.hpp"
 #include "fs_internal.hpp"
+#include "fs_plan.hpp"
 
 namespace fs {
 
@@ -181,51 +182,6 @@ __global__ __launch_bounds__(1024) void k_scan16(const uint64_t* __restrict__ h1
 hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s) {
     k_scan16<<<1, 1024, 0, s>>>(h16, p16);
     return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------
-// Plan: per digit, the exclusive prefix of its 256 bins (where each bin's
-// block starts in the pass output) and whether the digit is trivial (one
-// bin holds every key, so its stable scatter is the identity and the pass is
-// skipped).  Active passes ping-pong between the output and the temporary
-// buffer so that the last one lands in the output.  256 threads, thread b
-// owns bin b; h[j] is this thread's count of digit j.
-// ----------------------------------------------------------------------------
-__device__ void finish_plan(const uint64_t* h, int digits, uint64_t n, uint64_t* hist,
-                            uint64_t* base, uint32_t* plan) {
-    __shared__ uint64_t wsum[4];
-    __shared__ uint32_t trivial[8];
-    const int b = threadIdx.x;
-    for (int j = 0; j < digits; ++j) {
-        uint64_t total;
-        const uint64_t start = scan256_exclusive<uint64_t>(h[j], wsum, &total);
-        hist[j * kRadix + b] = h[j];
-        base[(uint64_t)j * 2 * kRadix + b] = start;  // buffer 0 of pass j
-        const int any = __syncthreads_or(h[j] == n);
-        if (b == 0) trivial[j] = any;
-    }
-    __syncthreads();
-    if (b == 0) {
-        int active_count = 0;
-        for (int j = 0; j < digits; ++j) active_count += trivial[j] ? 0 : 1;
-        int i = 0;
-        uint32_t prev = kBufIn;
-        for (int j = 0; j < 16; ++j) {
-            const bool act = j < digits && !trivial[j];
-            plan[4 * j] = act ? 1u : 0u;
-            plan[4 * j + 1] = 0;
-            plan[4 * j + 2] = 0;
-            plan[4 * j + 3] = 0;
-            if (act) {
-                const uint32_t dst = ((active_count - 1 - i) % 2 == 0) ? kBufOut : kBufTmp;
-                plan[4 * j + 1] = prev;
-                plan[4 * j + 2] = dst;
-                prev = dst;
-                ++i;
-            }
-        }
-        plan[kPlanCopy] = active_count == 0 ? 1u : 0u;
-    }
 }
 
 // Digit histograms of 16-bit keys as marginals of the 2^16-bin histogram:

@@ -3,13 +3,15 @@
 //
 // The paper's stable scatter phase (Section II) moves every key (and its
 // payload) to  start[digit] + (number of earlier keys with that digit).  The
-// prefix part comes from the exclusive scan of the digit's histogram (the
-// paper's GetIndex, Algorithm 3); the "earlier keys" part is split into
+// start comes from the exclusive scan of the digit's histogram (the paper's
+// GetIndex, Algorithm 3); the "earlier keys" part is split into
 // (a) keys of earlier tiles, found by decoupled look-back over per-tile bin
 // counts published in global memory, and (b) keys earlier in this tile,
-// found by wave-level matching of digits (ballot per digit bit) plus
-// per-wave running counters in LDS.  The tile is then staged in LDS in
-// digit order and written out as contiguous per-digit runs.
+// found per wave: every lane ORs its lane bit into an LDS word kept per
+// digit, so reading the word back gives each lane the full set of lanes
+// that share its digit (in any order of the atomic ORs), and the lowest of
+// them advances the wave's running count for the digit.  The tile is then
+// staged in LDS in digit order and written out as contiguous per-digit runs.
 //
 // Workgroups are persistent and take tiles from an ordered ticket counter,
 // so a tile only ever waits for tiles that are already running; every wait
@@ -19,15 +21,19 @@
 
 namespace fs {
 
+// predecessor tiles whose states one look-back round reads at once
+constexpr int kLookbackWindow = 16;
+
 template <typename K, typename V, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a) {
     constexpr int W = THREADS / kWave;
     constexpr int T = THREADS * ITEMS;
     constexpr bool kHasVals = !__is_same(V, NoVal);
     using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
+    static_assert(THREADS >= kRadix, "one thread per digit value in the look-back");
 
-    __shared__ uint32_t s_wcnt[W][kRadix];   // per-wave running counts, then wave prefixes
-    __shared__ uint32_t s_start[kRadix];     // tile-local start of each digit's block
+    __shared__ uint64_t s_peers[W][kRadix];  // lanes holding each digit in the current item
+    __shared__ uint32_t s_wcnt[W][kRadix];   // per-wave running counts, then tile offsets
     __shared__ uint64_t s_delta[kRadix];     // global destination of tile slot q is s_delta[d] + q
     __shared__ uint64_t s_wsum[4];
     __shared__ uint32_t s_ticket;
@@ -46,7 +52,9 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a) {
     }
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lane_bit = 1ull << lane;
     const uint64_t portion_end = a.portion_begin + a.portion_len;
+    for (int i = tid; i < W * kRadix; i += THREADS) (&s_peers[0][0])[i] = 0;
 
     for (;;) {
         if (tid == 0) s_ticket = add_agent(a.ticket, 1u);
@@ -65,84 +73,104 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a) {
         for (int k = 0; k < ITEMS; ++k) {
             const uint32_t idx = wbase + k * kWave + lane;
             if (idx < count) {
-                key[k] = src_k[tile_begin + idx];
-                if constexpr (kHasVals) val[k] = src_v[tile_begin + idx];
+                key[k] = __builtin_nontemporal_load(&src_k[tile_begin + idx]);
+                if constexpr (kHasVals) val[k] = __builtin_nontemporal_load(&src_v[tile_begin + idx]);
             }
         }
 #pragma unroll
         for (int i = 0; i < kRadix / kWave; ++i) s_wcnt[wave][lane + kWave * i] = 0;
         __builtin_amdgcn_wave_barrier();
 
-        // ---- rank inside the wave: peers with the same digit below this lane,
-        //      plus this wave's count of the digit in earlier items
+        // ---- rank inside the wave: lanes below with the same digit, plus this
+        //      wave's count of the digit in earlier items
         uint32_t rank[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t idx = wbase + k * kWave + lane;
-            const bool valid = idx < count;
+            const bool valid = wbase + k * kWave + lane < count;
             const uint32_t d = digit_of<K>(key[k], a.shift);
-            const uint64_t peers = match_digit8(d, ballot(valid));
-            const uint32_t below = lanes_below(peers);
-            uint32_t before = 0;
-            if (valid) before = s_wcnt[wave][d];
+            if (valid) atomicOr(&s_peers[wave][d], lane_bit);
             __builtin_amdgcn_wave_barrier();
-            if (valid && below == 0) s_wcnt[wave][d] = before + popc64(peers);
+            uint64_t peers = 0;
+            uint32_t before = 0;
+            if (valid) {
+                peers = s_peers[wave][d];
+                before = s_wcnt[wave][d];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t below = lanes_below(peers);
+            if (valid && below == 0) {
+                s_peers[wave][d] = 0;
+                s_wcnt[wave][d] = before + popc64(peers);
+            }
             __builtin_amdgcn_wave_barrier();
             rank[k] = before + below;
         }
         __syncthreads();
 
-        // ---- per digit: wave prefixes, tile count, publish, scan, look back
+        // ---- per digit (thread b < 256): tile count, publish, scan, look back
+        const int b = tid;
         uint32_t h = 0;
-        if (tid < kRadix) {
+        if (b < kRadix) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const uint32_t c = s_wcnt[w][tid];
-                s_wcnt[w][tid] = h;
-                h += c;
-            }
-            st_agent(&a.state[(uint64_t)t * kRadix + tid], (t == 0 ? kFlagPrefix : kFlagAggregate) | h);
+            for (int w = 0; w < W; ++w) h += s_wcnt[w][b];
+            st_agent(&a.state[(uint64_t)t * kRadix + b], (t == 0 ? kFlagPrefix : kFlagAggregate) | h);
         }
         uint64_t tile_total;
-        const uint32_t start = (uint32_t)scan256_exclusive<uint64_t>(tid < kRadix ? h : 0, s_wsum, &tile_total);
-        if (tid < kRadix) {
+        const uint32_t start = (uint32_t)scan256_exclusive<uint64_t>(b < kRadix ? h : 0, s_wsum, &tile_total);
+        if (b < kRadix) {
+            // wave offsets become tile offsets: slot of a key = s_wcnt[w][d] + rank
+            uint32_t run = start;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t c = s_wcnt[w][b];
+                s_wcnt[w][b] = run;
+                run += c;
+            }
             uint32_t excl = 0;
             if (t > 0) {
-                int64_t j = (int64_t)t - 1;
+                int64_t j = (int64_t)t - 1;  // nearest tile not yet folded in
                 uint32_t spins = 0;
-                for (;;) {
-                    const uint32_t sw = ld_agent(&a.state[(uint64_t)j * kRadix + tid]);
-                    if ((sw & ~kCountMask) == 0) {
-                        if (++spins > kSpinLimit) {
-                            atomicOr(a.err, 1u);
-                            break;
+                bool done = false;
+                while (!done) {
+                    uint32_t sw[kLookbackWindow];
+#pragma unroll
+                    for (int i = 0; i < kLookbackWindow; ++i)
+                        sw[i] = (j - i >= 0) ? ld_agent(&a.state[(uint64_t)(j - i) * kRadix + b]) : kFlagPrefix;
+#pragma unroll
+                    for (int i = 0; i < kLookbackWindow; ++i) {
+                        if (done) break;
+                        uint32_t w = sw[i];
+                        while ((w & ~kCountMask) == 0) {  // predecessor not published yet
+                            if (++spins > kSpinLimit) {
+                                atomicOr(a.err, 1u);
+                                w = kFlagPrefix;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            w = ld_agent(&a.state[(uint64_t)(j - i) * kRadix + b]);
                         }
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
+                        excl += w & kCountMask;
+                        done = (w & kFlagPrefix) != 0;
                     }
-                    excl += sw & kCountMask;
-                    if (sw & kFlagPrefix) break;
-                    if (--j < 0) {  // tile 0 always publishes a prefix
+                    j -= kLookbackWindow;
+                    if (!done && j < 0) {  // tile 0 always publishes a prefix
                         atomicOr(a.err, 2u);
-                        break;
+                        done = true;
                     }
                 }
-                st_agent(&a.state[(uint64_t)t * kRadix + tid], kFlagPrefix | (excl + h));
+                st_agent(&a.state[(uint64_t)t * kRadix + b], kFlagPrefix | (excl + h));
             }
-            s_start[tid] = start;
-            const uint64_t gbase = a.base_cur[tid] + excl;
-            s_delta[tid] = gbase - start;
-            if (t == a.tiles - 1) a.base_next[tid] = gbase + h;
+            const uint64_t gbase = a.base_cur[b] + excl;
+            s_delta[b] = gbase - start;
+            if (t == a.tiles - 1) a.base_next[b] = gbase + h;
         }
         __syncthreads();
 
         // ---- stage the tile in LDS in digit order
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t idx = wbase + k * kWave + lane;
-            if (idx < count) {
-                const uint32_t d = digit_of<K>(key[k], a.shift);
-                const uint32_t pos = s_start[d] + s_wcnt[wave][d] + rank[k];
+            if (wbase + k * kWave + lane < count) {
+                const uint32_t pos = s_wcnt[wave][digit_of<K>(key[k], a.shift)] + rank[k];
                 if (pos < (uint32_t)T) {
                     s_keys[pos] = key[k];
                     if constexpr (kHasVals) s_vals[pos] = val[k];
@@ -161,8 +189,8 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a) {
                 const K kk = s_keys[q];
                 const uint64_t dst = s_delta[digit_of<K>(kk, a.shift)] + q;
                 if (dst < a.n) {
-                    dst_k[dst] = kk;
-                    if constexpr (kHasVals) dst_v[dst] = s_vals[q];
+                    __builtin_nontemporal_store(kk, &dst_k[dst]);
+                    if constexpr (kHasVals) __builtin_nontemporal_store(s_vals[q], &dst_v[dst]);
                 } else {
                     atomicOr(a.err, 8u);
                 }
@@ -172,20 +200,29 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a) {
     }
 }
 
+#ifndef FS_SCATTER_THREADS
+#define FS_SCATTER_THREADS 256
+#endif
+#ifndef FS_SCATTER_ITEMS
+#define FS_SCATTER_ITEMS 16
+#endif
+
 ScatterShape scatter_shape(int key_bytes, int val_bytes) {
     (void)key_bytes;
     (void)val_bytes;
-    return ScatterShape{256, 16};
+    return ScatterShape{FS_SCATTER_THREADS, FS_SCATTER_ITEMS};
 }
 
 template <typename K, typename V>
 static hipError_t launch_kv(const ScatterArgs& a, hipStream_t s) {
-    constexpr int THREADS = 256, ITEMS = 16;
+    constexpr int THREADS = FS_SCATTER_THREADS, ITEMS = FS_SCATTER_ITEMS;
     static int grid = 0;
     if (grid == 0) {
         int per_cu = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scatter<K, V, THREADS, ITEMS>, THREADS, 0);
-        if (per_cu < 1) per_cu = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scatter<K, V, THREADS, ITEMS>, THREADS, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
         grid = per_cu * device_cu_count();
     }
     unsigned g = (unsigned)(a.tiles < (uint32_t)grid ? a.tiles : (uint32_t)grid);

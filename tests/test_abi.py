@@ -7,12 +7,13 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fs_sort.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 LIB = os.path.join(ROOT, "paper_2605_10390_amd", "libfsort.so")
 
 
 def declared_symbols():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(fs_[a-z_0-9]+)\s*\(", text)))
 
@@ -20,7 +21,7 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     syms = declared_symbols()
     for s in ("fs_sort_keys", "fs_sort_pairs", "fs_sort_segmented", "fs_digit_histograms",
-              "fs_status_string"):
+              "fs_status_string", "fs_profile_enable", "fs_profile_read"):
         assert s in syms
 
 
