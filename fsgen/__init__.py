@@ -227,3 +227,26 @@ def index_device(n, val_bytes=4, device="cuda", out=None):
     if rc != 0:
         raise RuntimeError(f"fsgen_index failed with code {rc}")
     return out
+
+
+# ------------------------------------------------------------ segment batches
+def lognormal_lengths(count, seed, median=2048.0, sigma=2.0, cap=1 << 22):
+    """Segment lengths L = clamp(round(exp(ln median + sigma * z)), 1, cap),
+    with z standard normal by the Box-Muller transform of two seeded uniform
+    draws (streams 5 and 6)."""
+    u1 = (rand64(seed, 5, 0, count) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u2 = (rand64(seed, 6, 0, count) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u1 = np.maximum(u1, 2.0 ** -53)
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    L = np.rint(np.exp(np.log(median) + sigma * z))
+    return np.clip(L, 1, cap).astype(np.int64)
+
+
+def segment_plan(count, seed, median=2048.0, sigma=2.0, cap=1 << 22):
+    """The batched workload: per segment its length, key width (16 for even
+    index, 32 for odd) and distribution (uniform or zipf by a seeded coin)."""
+    L = lognormal_lengths(count, seed, median, sigma, cap)
+    bits = np.where(np.arange(count) % 2 == 0, 16, 32)
+    coin = (rand64(seed, 7, 0, count) >> np.uint64(63)).astype(np.int64)
+    dist = np.where(coin == 1, "zipf", "uniform")
+    return L, bits, dist

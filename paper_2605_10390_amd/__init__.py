@@ -189,3 +189,75 @@ def digit_histograms(keys, digit_bits=8, workspace=None):
     if st != FS_OK:
         raise FsError(st, "fs_digit_histograms")
     return out
+
+
+# ------------------------------------------------------------- segmented sort
+import numpy as _np
+
+SEGMENT_DTYPE = _np.dtype([("keys_in", _np.uint64), ("keys_out", _np.uint64),
+                           ("vals_in", _np.uint64), ("vals_out", _np.uint64),
+                           ("n", _np.uint64), ("key_bits", _np.uint32), ("val_bytes", _np.uint32)])
+
+
+class SegmentBatch:
+    """A device-resident array of fs_segment descriptors.
+
+    `segments` is a sequence of (keys_in, keys_out, vals_in, vals_out)
+    tuples of GPU tensors (vals may be None).  The descriptors are built on
+    the host once and copied to the device; `run()` sorts every segment with
+    one fs_sort_segmented call.
+    """
+
+    def __init__(self, segments, device="cuda"):
+        m = len(segments)
+        desc = _np.zeros(m, dtype=SEGMENT_DTYPE)
+        total, biggest = 0, 0
+        for i, (ki, ko, vi, vo) in enumerate(segments):
+            n = ki.numel()
+            desc[i] = (ki.data_ptr() if n else 0, ko.data_ptr() if n else 0,
+                       vi.data_ptr() if vi is not None and n else 0,
+                       vo.data_ptr() if vo is not None and n else 0, n, _key_bits(ki),
+                       _VAL_BYTES[vi.dtype] if vi is not None else 0)
+            total += n
+            biggest = max(biggest, n)
+        self._keep = segments
+        self.from_descriptors(desc, total, biggest, device)
+
+    @classmethod
+    def from_array(cls, desc, total_keys, max_segment_keys, device="cuda", keep=None):
+        self = cls.__new__(cls)
+        self._keep = keep
+        self.from_descriptors(desc, total_keys, max_segment_keys, device)
+        return self
+
+    def from_descriptors(self, desc, total_keys, max_segment_keys, device):
+        self.count = int(desc.shape[0])
+        self.total_keys = int(total_keys)
+        self.max_segment_keys = int(max_segment_keys)
+        self.d_desc = torch.from_numpy(desc.view(_np.uint8).copy()).to(device)
+
+    def workspace_bytes(self):
+        size = ctypes.c_size_t(0)
+        st = lib().fs_sort_segmented(None, self.count, self.total_keys, self.max_segment_keys, 0,
+                                     None, ctypes.byref(size), None)
+        if st != FS_OK:
+            raise FsError(st, "fs_sort_segmented (workspace query)")
+        return size.value
+
+    def run(self, workspace=None, stream=None):
+        ws = workspace or Workspace(self.d_desc.device)
+        buf = ws.get(self.workspace_bytes())
+        size = ctypes.c_size_t(buf.numel())
+        s = stream if stream is not None else torch.cuda.current_stream(self.d_desc.device)
+        st = lib().fs_sort_segmented(_ptr(self.d_desc), self.count, self.total_keys,
+                                     self.max_segment_keys, 0, _ptr(buf), ctypes.byref(size),
+                                     ctypes.c_void_p(s.cuda_stream))
+        if st != FS_OK:
+            raise FsError(st, "fs_sort_segmented")
+        return ws
+
+
+def sort_segmented(segments, workspace=None):
+    """Sort every (keys_in, keys_out, vals_in, vals_out) segment independently
+    in one call; returns the workspace (its error word is 0 on success)."""
+    return SegmentBatch(segments).run(workspace)

@@ -304,9 +304,62 @@ fs_status fs_digit_histograms(const void* keys, uint64_t n, int key_bits, int di
 fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments, uint64_t total_keys,
                             uint64_t max_segment_keys, unsigned flags, void* workspace,
                             size_t* workspace_bytes, void* stream) {
-    (void)d_segments; (void)num_segments; (void)total_keys; (void)max_segment_keys;
-    (void)flags; (void)workspace; (void)workspace_bytes; (void)stream;
-    return FS_ERR_UNSUPPORTED;
+    using namespace fs;
+    if (flags != FS_FLAG_NONE || !workspace_bytes) return FS_ERR_INVALID_ARG;
+    if (max_segment_keys > kSegMaxKeys) return FS_ERR_UNSUPPORTED;
+    if (total_keys > kMaxKeys) return FS_ERR_INVALID_ARG;
+    const uint32_t nseg = num_segments;
+    const uint32_t max_tiles = seg_max_tiles(total_keys, nseg);
+    const uint64_t nl_max = std::min<uint64_t>(nseg, total_keys / (kSegMinSmallCap + 1) + 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    const size_t o_err = take(4 * (1 + 128));
+    const size_t o_small = take(4ull * nseg);
+    const size_t o_large = take(4ull * 9 * nseg);
+    const size_t o_tp = take(4ull * (nseg + 1));
+    const size_t o_ep = take(8ull * (nseg + 1));
+    const size_t o_ts = take(4ull * max_tiles);
+    const size_t o_hist = take(4ull * nl_max * 8 * kRadix);
+    const size_t o_plan = take(4ull * nl_max * 9);
+    const size_t o_state = take(4ull * max_tiles * kRadix);
+    const size_t o_tk = take(8ull * total_keys);
+    const size_t o_tv = take(8ull * total_keys);
+    const size_t need = off;
+    if (!workspace) {
+        *workspace_bytes = need;
+        return FS_OK;
+    }
+    if (nseg == 0) return FS_OK;
+    if (!d_segments || !aligned(workspace, 256) || !aligned(d_segments, 8)) return FS_ERR_INVALID_ARG;
+    if (*workspace_bytes < need) return FS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(workspace);
+    SegCtx x;
+    x.segs = d_segments;
+    x.nseg = nseg;
+    x.max_seg = max_segment_keys;
+    x.total_keys = total_keys;
+    x.max_tiles = max_tiles;
+    x.err = reinterpret_cast<uint32_t*>(w + o_err);
+    x.ctr = x.err + 1;
+    x.small_list = reinterpret_cast<uint32_t*>(w + o_small);
+    x.large_list = reinterpret_cast<uint32_t*>(w + o_large);
+    x.tile_prefix = reinterpret_cast<uint32_t*>(w + o_tp);
+    x.elem_prefix = reinterpret_cast<uint64_t*>(w + o_ep);
+    x.tile_seg = reinterpret_cast<uint32_t*>(w + o_ts);
+    x.hist = reinterpret_cast<uint32_t*>(w + o_hist);
+    x.plan = reinterpret_cast<uint32_t*>(w + o_plan);
+    x.state = reinterpret_cast<uint32_t*>(w + o_state);
+    x.tmp_k = w + o_tk;
+    x.tmp_v = w + o_tv;
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.err, 1 + 128, 0, s));
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.state, (uint64_t)max_tiles * kRadix, 0, s));
+    FS_LAUNCH(FS_KERNEL_SEGMENTED, total_keys, launch_segmented(x, s));
+    return FS_OK;
 }
 
 const char* fs_status_string(fs_status s) {

@@ -100,4 +100,31 @@ __device__ __forceinline__ T scan256_exclusive(T x, T* wsum, T* total) {
     return before + inc - x;
 }
 
+// Stable rank of one item per lane among the lanes of this wave: every
+// valid lane ORs its lane bit into peers[d] (LDS, one 64-bit word per
+// digit value, all zero on entry), so the word read back is the set of
+// lanes sharing its digit whatever order the ORs took; the lowest of them
+// clears the word and advances cnt[d], the wave's running count of d.
+// Returns (count of d before this item) + (peers below this lane).
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint64_t* peers_w,
+                                              uint32_t* cnt_w) {
+    const uint64_t lane_bit = 1ull << (threadIdx.x & 63);
+    if (valid) atomicOr(&peers_w[d], lane_bit);
+    __builtin_amdgcn_wave_barrier();
+    uint64_t peers = 0;
+    uint32_t before = 0;
+    if (valid) {
+        peers = peers_w[d];
+        before = cnt_w[d];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t below = lanes_below(peers);
+    if (valid && below == 0) {
+        peers_w[d] = 0;
+        cnt_w[d] = before + popc64(peers);
+    }
+    __builtin_amdgcn_wave_barrier();
+    return before + below;
+}
+
 }  // namespace fs

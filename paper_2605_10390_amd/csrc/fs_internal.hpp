@@ -1,6 +1,8 @@
 // Host-side internals: workspace layout and kernel launchers.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "fs_sort.h"
 #include <stddef.h>
 #include <stdint.h>
 
@@ -136,5 +138,32 @@ hipError_t timed(int kind, uint64_t keys, hipStream_t s, F&& launch) {
     profile_close(kind, keys, s, b);
     return r;
 }
+
+// ---- batched segmented sort (segmented.hip) --------------------------------
+constexpr uint32_t kSegSmallBytes = 32768;           // LDS bytes per buffer of a small segment
+constexpr uint64_t kSegMaxKeys = (1ull << 23) - 1;  // largest segment (look-back counts are 23-bit)
+constexpr uint32_t kSegMinSmallCap = (kSegSmallBytes - 16) / 16;
+
+struct SegCtx {
+    const fs_segment* segs;
+    uint32_t nseg;
+    uint64_t max_seg;
+    uint64_t total_keys;
+    uint32_t max_tiles;
+    uint32_t* err;
+    uint32_t* ctr;          // queue counters, tile totals, tickets
+    uint32_t* small_list;   // [nseg]
+    uint32_t* large_list;   // [9][nseg]
+    uint32_t* tile_prefix;  // [nseg + 1] (current class)
+    uint64_t* elem_prefix;  // [nseg + 1] (current class)
+    uint32_t* tile_seg;     // [max_tiles]
+    uint32_t* hist;         // [large segments][8][256]
+    uint32_t* plan;         // [large segments][9]
+    uint32_t* state;        // [max_tiles][256]
+    void* tmp_k;
+    void* tmp_v;
+};
+uint32_t seg_max_tiles(uint64_t total_keys, uint32_t nseg);
+hipError_t launch_segmented(const SegCtx& x, hipStream_t s);
 
 }  // namespace fs
