@@ -105,18 +105,135 @@ def cpu_baseline(keys_dev, vals_dev, key_bits, val_bytes, budget_s=12.0):
                       f" sorted {reps}x single-threaded by the C oracle, {elapsed:.1f} s total"}
 
 
+def build_c3(dev, count=100000, seed=None):
+    """The batched workload: `count` segments with log-normal lengths
+    (median 2048, sigma 2, capped at 2^22), 16-bit keys for even and 32-bit
+    for odd segments, uniform or Zipf by a seeded coin, keys only.  Keys of
+    each width class come from one device-generated array per distribution;
+    segments are consecutive slices of it."""
+    import numpy as np
+    import torch
+    import fsgen
+    import paper_2605_10390_amd as fs
+    seed = fsgen.seed_for(3, 0) if seed is None else seed
+    L, bits, dist = fsgen.segment_plan(count, seed)
+    pools = {}
+    desc = np.zeros(count, dtype=fs.SEGMENT_DTYPE)
+    keep = []
+    for b in (16, 32):
+        for dname in ("uniform", "zipf"):
+            sel = np.flatnonzero((bits == b) & (dist == dname))
+            tot = int(L[sel].sum())
+            if tot == 0:
+                continue
+            # Zipf is drawn over 65536 ranks (16-bit values) for either width
+            g = fsgen.keys_device(dname, b if dname == "uniform" else 16, tot,
+                                  seed + b + (dname == "zipf"), device=dev)
+            if b == 32 and dname == "zipf":
+                g = g.to(torch.int32).view(torch.uint32)  # Zipf ranks as 32-bit keys
+            out = torch.empty_like(g)
+            keep += [g, out]
+            esz = b // 8
+            offs = np.concatenate([[0], np.cumsum(L[sel])[:-1]]).astype(np.uint64)
+            desc["keys_in"][sel] = np.uint64(g.data_ptr()) + offs * np.uint64(esz)
+            desc["keys_out"][sel] = np.uint64(out.data_ptr()) + offs * np.uint64(esz)
+            desc["n"][sel] = L[sel].astype(np.uint64)
+            desc["key_bits"][sel] = b
+            pools[(b, dname)] = (g, out, sel, offs)
+    batch = fs.SegmentBatch.from_array(desc, int(L.sum()), int(L.max()), device=dev, keep=keep)
+    return batch, desc, pools, L
+
+
+def run_c3(args):
+    import ctypes
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2605_10390_amd as fs
+    dev = torch.device("cuda:0")
+    batch, desc, pools, L = build_c3(dev)
+    n = batch.total_keys
+    ws = fs.Workspace(dev)
+    ws.get(batch.workspace_bytes())
+    graph = fs.CapturedSort(lambda: batch.run(ws), dev)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    print(f"[bench] c3: {batch.count} segments, {n} keys; warmup done", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    if ws.error_word() != 0:
+        raise SystemExit(f"device error word {ws.error_word():#x}")
+    # spot check: sampled segments against the oracle
+    rng = np.random.default_rng(0)
+    for i in rng.choice(batch.count, size=24, replace=False):
+        b = int(desc["key_bits"][i])
+        for (pb, dname), (g, out, sel, offs) in pools.items():
+            if pb != b:
+                continue
+            pos = np.searchsorted(sel, i)
+            if pos < len(sel) and sel[pos] == i:
+                o, m = int(offs[pos]), int(L[i])
+                assert np.array_equal(out[o:o + m].cpu().numpy(), oracle.sort(g[o:o + m].cpu().numpy())), i
+    # baseline: one fs_sort_keys call per segment from a host loop, no graphs
+    Lb = fs.lib()
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    wsb = fs.Workspace(dev)
+    need = max(fs.sort_keys_workspace_bytes(int(L.max()), 16), fs.sort_keys_workspace_bytes(int(L.max()), 32))
+    buf = wsb.get(need)
+    size = ctypes.c_size_t(buf.numel())
+    bp = ctypes.c_void_p(buf.data_ptr())
+    kin, kout, nn, kb = (desc["keys_in"].tolist(), desc["keys_out"].tolist(), desc["n"].tolist(),
+                         desc["key_bits"].tolist())
+    torch.cuda.synchronize()
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b0.record()
+    for i in range(batch.count):
+        size.value = buf.numel()
+        r = Lb.fs_sort_keys(ctypes.c_void_p(kin[i]), ctypes.c_void_p(kout[i]), nn[i], kb[i], 0, bp,
+                            ctypes.byref(size), st)
+        if r != 0:
+            raise SystemExit(f"fs_sort_keys failed on segment {i}: {r}")
+    b1.record()
+    torch.cuda.synchronize()
+    ms_loop = b0.elapsed_time(b1)
+    gk = n / (ms_batched / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(gk, 3), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u16/u32 mixed", "data": "synthetic",
+        "config": {"workload": f"batched segmented sort: {batch.count} segments, log-normal lengths "
+                               "(median 2048, sigma 2, cap 2^22), half u16 half u32, uniform/Zipf, keys only",
+                   "n": n, "segments": batch.count, "max_segment": int(L.max()),
+                   "parallelism": "single GPU", "graph": True},
+        "one_launch_per_sort": {"ms": round(ms_loop, 3), "gkeys_s": round(n / (ms_loop / 1e3) / 1e9, 3),
+                                "calls": batch.count},
+        "batched_speedup": round(ms_loop / ms_batched, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design in DESIGN.md, not a measured path)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c3":
+        return run_c3(args)
 
     import torch
     import ctypes

@@ -257,6 +257,33 @@ class SegmentBatch:
         return ws
 
 
+class CapturedSort:
+    """A hipGraph of one sort call, replayed with `replay()`.
+
+    The library issues no memset and allocates nothing inside a call, so its
+    whole launch sequence (fills, histograms, plan, passes) can be captured.
+    The graph keeps the buffer addresses it was captured with; for a
+    segmented sort the descriptors are read from device memory at run time,
+    so new data in the same buffers, or rewritten descriptors, are sorted by
+    a replay.
+    """
+
+    def __init__(self, fn, device="cuda"):
+        self.graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize(device)
+        side = torch.cuda.Stream(device)  # default priority
+        side.wait_stream(torch.cuda.current_stream(device))
+        with torch.cuda.stream(side):
+            fn()  # warm-up outside capture (first-touch, occupancy queries)
+        torch.cuda.current_stream(device).wait_stream(side)
+        torch.cuda.synchronize(device)
+        with torch.cuda.graph(self.graph):
+            fn()
+
+    def replay(self):
+        self.graph.replay()
+
+
 def sort_segmented(segments, workspace=None):
     """Sort every (keys_in, keys_out, vals_in, vals_out) segment independently
     in one call; returns the workspace (its error word is 0 on success)."""

@@ -119,3 +119,31 @@ def test_segmented_repeatable(gpu):
         assert torch.equal(a.view(torch.int16 if a.dtype == torch.uint16 else torch.int32),
                            d[1].view(torch.int16 if a.dtype == torch.uint16 else torch.int32))
     check(host, devs)
+
+
+def test_graph_replays_match_eager(gpu):
+    """The captured launch sequence, replayed several times with eager work
+    and synchronisations in between, gives the eager result every time."""
+    host, devs = [], []
+    for i in range(60):
+        h, d = make_segment(int(300 + 4111 * (i % 7) + 37 * i), (16, 32, 64)[i % 3], (0, 4)[i % 2],
+                            "uniform", 100 + i, gpu)
+        host.append(h)
+        devs.append(d)
+    batch = fs.SegmentBatch(devs)
+    ws = fs.Workspace(gpu)
+    ws.get(batch.workspace_bytes())
+    g = fs.CapturedSort(lambda: batch.run(ws), gpu)
+    for r in range(3):
+        signed = {1: torch.int8, 2: torch.int16, 4: torch.int32, 8: torch.int64}
+        for d in devs:
+            for t in (d[1], d[3]):
+                if t is not None and t.numel():
+                    t.view(signed[t.element_size()]).zero_()
+        junk = torch.randn(1 << 20, device=gpu).sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert ws.error_word() == 0
+        check(host, devs)
+        del junk
