@@ -210,8 +210,8 @@ def keys_device(dist, key_bits, n, seed, device="cuda", out=None):
                         table.data_ptr() if table is not None else None, stream)
     if rc != 0:
         raise RuntimeError(f"fsgen_keys failed with code {rc}")
-    if table is not None:
-        torch.cuda.current_stream(out.device).synchronize()  # table freed after use
+    if table is not None:  # freed only once the stream is past the generator
+        table.record_stream(torch.cuda.current_stream(out.device))
     return out
 
 

@@ -199,6 +199,15 @@ SEGMENT_DTYPE = _np.dtype([("keys_in", _np.uint64), ("keys_out", _np.uint64),
                            ("n", _np.uint64), ("key_bits", _np.uint32), ("val_bytes", _np.uint32)])
 
 
+def sort_segmented_workspace_bytes(count, total_keys, max_segment_keys):
+    size = ctypes.c_size_t(0)
+    st = lib().fs_sort_segmented(None, int(count), int(total_keys), int(max_segment_keys), 0, None,
+                                 ctypes.byref(size), None)
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_segmented (workspace query)")
+    return size.value
+
+
 class SegmentBatch:
     """A device-resident array of fs_segment descriptors.
 
@@ -237,12 +246,7 @@ class SegmentBatch:
         self.d_desc = torch.from_numpy(desc.view(_np.uint8).copy()).to(device)
 
     def workspace_bytes(self):
-        size = ctypes.c_size_t(0)
-        st = lib().fs_sort_segmented(None, self.count, self.total_keys, self.max_segment_keys, 0,
-                                     None, ctypes.byref(size), None)
-        if st != FS_OK:
-            raise FsError(st, "fs_sort_segmented (workspace query)")
-        return size.value
+        return sort_segmented_workspace_bytes(self.count, self.total_keys, self.max_segment_keys)
 
     def run(self, workspace=None, stream=None):
         ws = workspace or Workspace(self.d_desc.device)
