@@ -31,7 +31,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Gkeys/s & % of HBM peak (16-bit, 4 GB); batched vs one-launch-per-sort"
 HBM_PEAK_GBPS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "scatter_u16u32_uniform_2e31_pmc.json")
-KERNEL_SOURCES = ["paper_2605_10390_amd/csrc/scatter.hip", "paper_2605_10390_amd/csrc/fs_device.hpp"]
+KERNEL_SOURCES = ["paper_2605_10390_amd/csrc/chunked.hip", "paper_2605_10390_amd/csrc/fs_device.hpp"]
+DOMINANT = {"c1": "k_range_scatter16", "c0": "k_expand16", "c2a": "k_scatter", "c2b": "k_scatter"}
+COPY_PROBE_BYTES = 4 << 30
 
 WORKLOADS = {
     # name: (key_bits, val_bytes, log2 n, distribution, description)
@@ -274,6 +276,38 @@ def run_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def pmc_summary(fetch_csv, write_csv, kernel, out_path, command):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch) of `bench.py --copy-probe` into HBM bytes per launch of
+    `kernel`.  Each counter is scaled by what it reads for the plain 4 GiB
+    device copy the probe runs first (4 GiB read, 4 GiB written)."""
+    import csv
+    import collections
+
+    def per_dispatch(path):
+        acc = collections.OrderedDict()
+        for r in csv.DictReader(open(path)):
+            key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+        return acc
+
+    f, w = per_dispatch(fetch_csv), per_dispatch(write_csv)
+    copy_f = max(v for (d, k), v in f.items() if "copyBuffer" in k)
+    copy_w = max(v for (d, k), v in w.items() if "copyBuffer" in k)
+    ff, wf = COPY_PROBE_BYTES / (copy_f * 1024.0), COPY_PROBE_BYTES / (copy_w * 1024.0)
+    kf = [v * 1024.0 * ff for (d, k), v in f.items() if kernel in k]
+    kw = [v * 1024.0 * wf for (d, k), v in w.items() if kernel in k]
+    summary = {"kernel": kernel, "launches": len(kf),
+               "fetch_bytes_per_launch": sum(kf) / len(kf), "write_bytes_per_launch": sum(kw) / len(kw),
+               "hbm_bytes_per_launch": (sum(kf) + sum(kw)) / len(kf),
+               "fetch_scale": ff, "write_scale": wf,
+               "calibration": "plain device copy of 4 GiB (rocclr copyBuffer) in the same run",
+               "kernel_source_sha256_16": kernel_source_hash(), "command": command}
+    with open(out_path, "w") as fo:
+        json.dump(summary, fo, indent=1)
+    print(json.dumps(summary))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,7 +316,16 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4"])
     ap.add_argument("--jobs", type=int, default=1000, help="served-stream prefix length (c4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 4 GiB device copy first (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs of this bench into profiles/")
     args = ap.parse_args()
+    if args.pmc_summary:
+        cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- "
+               f"python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu-baseline --copy-probe")
+        return pmc_summary(args.pmc_summary[0], args.pmc_summary[1], DOMINANT[args.workload],
+                           PMC_SUMMARY, cmd)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design in DESIGN.md, not a measured path)", file=sys.stderr)
@@ -304,6 +347,13 @@ def main():
     seed = fsgen.seed_for({"c0": 0, "c1": 1, "c2a": 2, "c2b": 2}[args.workload], 0)
     keys = fsgen.keys_device(dist, key_bits, n, seed, device=dev)
     vals = fsgen.index_device(n, val_bytes, device=dev) if val_bytes else None
+    if args.copy_probe:  # counter calibration: a plain copy of known size
+        a = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ko = torch.empty_like(keys)
     vo = torch.empty_like(vals) if vals is not None else None
     ws = fs.Workspace(dev)
@@ -366,17 +416,16 @@ def main():
                        "expand": key_bits // 8}.get(name)
             if per_key and kinfo["ms_total"] > 0:
                 kinfo["gbps"] = kinfo["keys"] * per_key / (kinfo["ms_total"] / 1e3) / 1e9
+    dom_name = DOMINANT[args.workload]
     if key_bits == 16 and val_bytes == 0:
         dom = kernels["expand"]
         dom_bytes_per_key = 2  # the expansion writes every key once
-        dom_name = "k_expand16"
     else:
         dom = kernels["scatter"]
         dom_bytes_per_key = scatter_bytes_per_key(key_bits, val_bytes)
-        dom_name = "k_scatter"
     achieved = (dom["keys"] / dom["launches"]) * dom_bytes_per_key / (dom["ms_avg"] / 1e3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(src_hash) if dom_name == "k_scatter" and args.workload == "c1" else None
+    traffic = read_traffic(src_hash) if args.workload == "c1" else None
     out = {
         "metric": METRIC,
         "value": round(gkeys, 3),
