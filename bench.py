@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Gkeys/s & % of HBM peak (16-bit, 4 GB); batched vs one-launch-per-sort"
 HBM_PEAK_GBPS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "scatter_u16u32_uniform_2e31_pmc.json")
-KERNEL_SOURCES = ["paper_2605_10390_amd/csrc/chunked.hip", "paper_2605_10390_amd/csrc/fs_device.hpp"]
-DOMINANT = {"c1": "k_range_scatter16", "c0": "k_expand16", "c2a": "k_scatter", "c2b": "k_scatter"}
+KERNEL_SOURCES = ["paper_2605_10390_amd/csrc/tiled.hip", "paper_2605_10390_amd/csrc/fs_device.hpp"]
+DOMINANT = {"c1": "k_tile_scatter", "c0": "k_expand16", "c2a": "k_tile_scatter", "c2b": "k_tile_scatter"}
 COPY_PROBE_BYTES = 4 << 30
 
 WORKLOADS = {

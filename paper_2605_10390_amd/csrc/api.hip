@@ -47,16 +47,37 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
     L.plan = take(4ull * kPlanWords);
     L.hist = take(8ull * 8 * kRadix);
     L.base = take(8ull * 8 * 2 * kRadix);
-    if (L.compressed16) {
+    if (L.compressed16 && L.expand16) {
         L.part = take(4ull * L.hist_groups * kHist16Words);
         L.wrap = take(4ull * 2 * kHist16Words);
         L.h16 = take(8ull * 65536);
         L.p16 = take(8ull * 65537);
-    } else {
-        L.part = take(4ull * L.hist_groups * L.digits * kRadix);
     }
-    L.chunked16 = key_bytes == 2 && val_bytes != 0 && n < (1ull << 32);
-    if (L.chunked16) {
+    L.tiled = !L.expand16;
+    L.chunked16 = false;
+    if (L.tiled) {
+        L.compressed16 = false;
+        L.tile = (uint32_t)tiled_shape(key_bytes, val_bytes).tile();
+        L.tiles = std::max<uint64_t>(ceil_div(n, L.tile), 1);
+        L.tile_blocks = ceil_div(L.tiles, 65536 / L.tile);
+        L.tile_supers = ceil_div(L.tile_blocks, kSuperBlock);
+        L.hist_groups = (uint32_t)std::min<uint64_t>(L.tile_blocks, 4ull * num_cus);
+        static const int per_cu[3][3] = {
+            {0, tiled_scatter_per_cu(2, 4), tiled_scatter_per_cu(2, 8)},
+            {tiled_scatter_per_cu(4, 0), tiled_scatter_per_cu(4, 4), tiled_scatter_per_cu(4, 8)},
+            {tiled_scatter_per_cu(8, 0), tiled_scatter_per_cu(8, 4), tiled_scatter_per_cu(8, 8)}};
+        const int ki = key_bytes == 2 ? 0 : key_bytes == 4 ? 1 : 2, vi = val_bytes / 4;
+        L.scatter_groups = (uint32_t)std::max(1, num_cus * std::max(1, per_cu[ki][vi]));
+        L.part = take(4ull * L.hist_groups * L.digits * kRadix);
+        L.th = take(2ull * kRadix * L.tiles);
+        L.bsum = take(4ull * kRadix * L.tile_blocks);
+        L.ssum = take(4ull * kRadix * L.tile_supers);
+        L.sbase = take(8ull * kRadix * L.tile_supers);
+        L.tile_tickets = take(4ull * L.digits * kXcds * kTicketStride);
+        L.sink = take(16);
+        L.tmp_keys = take((size_t)n * key_bytes);
+        if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
+    } else if (L.chunked16) {
         static const int per_cu4 = range_scatter16_per_cu(4), per_cu8 = range_scatter16_per_cu(8);
         const uint64_t resident = (uint64_t)num_cus * (val_bytes == 8 ? per_cu8 : per_cu4);
         L.chunks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), resident);
@@ -137,6 +158,41 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     uint32_t* part = reinterpret_cast<uint32_t*>(w + L.part);
 
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(err, 1 + 8ull * L.portions, 0, s));
+
+    if (L.tiled) {
+        TiledArgs a;
+        a.in_k = keys_in;
+        a.out_k = keys_out;
+        a.tmp_k = w + L.tmp_keys;
+        a.in_v = vals_in;
+        a.out_v = vals_out;
+        a.tmp_v = val_bytes ? w + L.tmp_vals : nullptr;
+        a.n = n;
+        a.tiles = L.tiles;
+        a.tile = L.tile;
+        a.block_tiles = 65536 / L.tile;
+        a.plan = plan;
+        a.base = base;
+        a.th = reinterpret_cast<uint32_t*>(w + L.th);
+        a.bsum = reinterpret_cast<uint32_t*>(w + L.bsum);
+        a.ssum = reinterpret_cast<uint32_t*>(w + L.ssum);
+        a.sbase = reinterpret_cast<uint64_t*>(w + L.sbase);
+        a.part = part;
+        a.tickets = reinterpret_cast<uint32_t*>(w + L.tile_tickets);
+        a.sink = w + L.sink;
+        a.err = err;
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan8(part, L.hist_groups, L.digits, n, hist, base, plan, s));
+        for (int j = 0; j < L.digits; ++j) {
+            if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
+            FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
+            FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, s));
+        }
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
+        if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
+        return FS_OK;
+    }
 
     if (L.chunked16) {
         Plan16 p;

@@ -34,6 +34,10 @@ struct SortLayout {
     bool expand16 = false;    // 16-bit keys only: histogram + expansion
     bool compressed16 = false;  // digit histograms from the compressed 2^16-bin histogram
     bool chunked16 = false;     // 16-bit keys + payload: per-chunk histograms, no look-back
+    bool tiled = false;         // reduce-then-scan over fixed tiles
+    uint32_t tile = 0, scatter_groups = 0;
+    uint64_t tiles = 0, tile_blocks = 0, tile_supers = 0;
+    size_t th = 0, bsum = 0, ssum = 0, sbase = 0, tile_tickets = 0, sink = 0;
     uint32_t chunks = 0, ranges1 = 0, log_capacity = 0;
     size_t J = 0, log = 0, H = 0, RP = 0, O0 = 0, O1 = 0, start1 = 0, run1 = 0;
     uint32_t hist_groups = 0;   // workgroups of the histogram kernel
@@ -124,6 +128,41 @@ hipError_t launch_joint16(const void* keys, uint64_t n, int key_bytes, int shift
 hipError_t launch_plan_chunked16(const Plan16& p, uint64_t n, hipStream_t s);
 hipError_t launch_range_scatter16(const RangeArgs& a, uint32_t groups, int val_bytes, hipStream_t s);
 int range_scatter16_per_cu(int val_bytes);  // resident workgroups per CU
+
+// ---- tiled reduce-then-scan path (tiled.hip) -------------------------------
+constexpr uint64_t kSuperBlock = 256;  // blocks per super-block of the offset scan
+constexpr uint32_t kXcds = 8;          // tile groups of a scatter launch (one per XCD)
+constexpr uint32_t kTicketStride = 32; // words between ticket counters (one 128-byte line each)
+
+struct TiledArgs {
+    const void* in_k;
+    void* out_k;
+    void* tmp_k;
+    const void* in_v;
+    void* out_v;
+    void* tmp_v;
+    uint64_t n;
+    uint64_t tiles;         // ceil(n / tile)
+    uint32_t tile;          // keys per tile (the scatter's threads * items)
+    uint32_t block_tiles;   // tiles per block: 65536 / tile
+    const uint32_t* plan;
+    const uint64_t* base;   // plan: start of every digit value in each pass output
+    uint32_t* th;           // [tiles][256] 16-bit counts of the pass digit, then block prefixes
+    uint32_t* bsum;         // [blocks][256] block totals, then super-block prefixes
+    uint32_t* ssum;         // [super-blocks][256] super-block totals
+    uint64_t* sbase;        // [super-blocks][256] super-block starts in the pass output
+    uint32_t* part;         // [groups][digits][256] first-pass workgroup totals
+    uint32_t* tickets;      // [passes][kXcds][kTicketStride] tile tickets, zero on entry
+    void* sink;             // 16 bytes that absorb the stores of out-of-range lanes
+    uint32_t* err;
+};
+
+ScatterShape tiled_shape(int key_bytes, int val_bytes);
+int tiled_scatter_per_cu(int key_bytes, int val_bytes);
+hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s);
+hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s);
+hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
+                               hipStream_t s);
 
 // ---- per-kernel event timing (include/fs_profile.h) ------------------------
 void profile_mark(int kind, uint64_t keys, hipStream_t s, hipEvent_t* begin_out);

@@ -1,0 +1,542 @@
+// Stable LSD sort by reduce-then-scan over fixed tiles, with no waiting
+// between workgroups.
+//
+// The paper builds a histogram of narrow counters once per batch (Section
+// III-A/B, Algorithm 1; counter width tapered to the batch, Section
+// III-D.1) and reads positions back as prefix sums (GetIndex, Algorithm 3).
+// Here a batch is a tile of T keys.  Each pass of one 8-bit digit runs three
+// steps:
+//
+//   1. tile histograms: for every tile, the 256 counts of the pass digit as
+//      packed 16-bit counters (T < 2^16, so a tile's counters cannot wrap),
+//      turned at once into prefixes inside blocks of tiles; the first pass
+//      also accumulates every digit's global counts for the pass plan;
+//   2. offsets: the remaining levels of the exclusive prefix of every digit
+//      over the tiles, added to the digit's start in the pass output (the
+//      plan's exclusive scan);
+//   3. scatter: each tile is ranked per wave, staged in LDS in digit order
+//      and written as contiguous per-digit runs starting at its offsets.
+//
+// Write locality: the tiles are split into 8 contiguous groups, one per
+// XCD (workgroup g of a launch runs on XCD g mod 8), and the workgroups of a
+// group walk their group's tiles in order.  So the tiles in flight on one
+// XCD at any time are consecutive, their runs of every digit are adjacent in
+// the output, and the cache lines that two runs share meet in that XCD's L2
+// and leave it whole.  The split only steers performance: every offset is
+// precomputed, so results do not depend on where a workgroup runs.
+#include "fs_device.hpp"
+#include "fs_internal.hpp"
+
+#include <type_traits>
+
+namespace fs {
+
+constexpr int kTileHistThreads = 512;
+
+template <typename K>
+__device__ __forceinline__ const K* pass_source(const TiledArgs& a, uint32_t sel) {
+    return static_cast<const K*>(sel == kBufIn ? a.in_k : sel == kBufOut ? a.out_k : a.tmp_k);
+}
+
+// ---------------------------------------------------------------------------
+// Step 1: tile histograms and the first offset level.
+//
+// A block is 65536 / T consecutive tiles; every histogram workgroup owns a
+// contiguous run of whole blocks and walks it in order, kHistTilesPer tiles
+// per step.  The counts of a tile are kept in LDS as packed 16-bit counters
+// (bins 2w and 2w+1 in word w; a tile holds at most T < 2^16 keys, so the
+// halves cannot carry), one copy per wave parity and tile of the step, and
+// double-buffered between steps so that one barrier per step suffices.
+// The workgroup then writes, per tile t and digit value d,
+//   th[t][d]   = counts of d in the tiles of t's block before t  (16 bits,
+//                packed in pairs like the counters: at most 65536 - T)
+//   bsum[b][d] = total count of d in block b.
+// With FIRST the workgroup also counts every other digit of its keys, and
+// part[g][j][b] receives its totals of digit j == b for the pass plan.
+// ---------------------------------------------------------------------------
+constexpr int kHistTilesPer = 4;
+constexpr int kHistCopies = 2;
+
+template <typename K, bool FIRST>
+__global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int pass) {
+    constexpr int D = sizeof(K);
+    constexpr int VK = 16 / sizeof(K);
+    constexpr int DX = FIRST ? D : 1;  // digits counted per workgroup (index 0 unused)
+    constexpr int SETW = kRadix / 2;   // words of one packed tile histogram
+    __shared__ uint32_t s_t[2][kHistTilesPer][kHistCopies][SETW];
+    __shared__ uint32_t s_all[DX][kRadix];
+
+    const K* src;
+    if constexpr (FIRST) {
+        src = static_cast<const K*>(a.in_k);
+    } else {
+        if (!a.plan[4 * pass]) return;
+        src = pass_source<K>(a, a.plan[4 * pass + 1]);
+    }
+    const int shift = 8 * pass;
+    const int tid = threadIdx.x, wave = tid >> 6, copy = wave % kHistCopies;
+    for (int i = tid; i < 2 * kHistTilesPer * kHistCopies * SETW; i += kTileHistThreads) (&s_t[0][0][0][0])[i] = 0;
+    for (int i = tid; i < DX * kRadix; i += kTileHistThreads) (&s_all[0][0])[i] = 0;
+
+    const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
+    const uint64_t blo = blocks * blockIdx.x / gridDim.x, bhi = blocks * (blockIdx.x + 1) / gridDim.x;
+    const uint64_t tlo = blo * a.block_tiles;
+    const uint64_t thi = bhi * a.block_tiles < a.tiles ? bhi * a.block_tiles : a.tiles;
+    const uint64_t T = a.tile;
+    const uintptr_t base_addr = reinterpret_cast<uintptr_t>(src);
+
+    // thread w < 128 owns bins 2w and 2w+1: running counts inside the
+    // current block and workgroup totals
+    uint32_t run_lo = 0, run_hi = 0, tot_lo = 0, tot_hi = 0;
+    int par = 0;
+    __syncthreads();
+    for (uint64_t t0 = tlo; t0 < thi; t0 += kHistTilesPer, par ^= 1) {
+        const uint64_t lo = t0 * T;
+        const uint64_t hi_t = t0 + kHistTilesPer < thi ? t0 + kHistTilesPer : thi;
+        const uint64_t hi = hi_t * T < a.n ? hi_t * T : a.n;
+        const uint32_t cnt = (uint32_t)(hi - lo);
+        const uintptr_t b0 = base_addr + lo * sizeof(K), b1 = base_addr + hi * sizeof(K);
+        const uintptr_t v0 = b0 & ~(uintptr_t)15;
+        const uint32_t nv = (uint32_t)((((b1 + 15) & ~(uintptr_t)15) - v0) / 16);
+        // derived from src (not from the integer address) so that the
+        // compiler keeps these global-memory loads
+        const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - (b0 - v0) / sizeof(K)));
+        for (uint32_t v = tid; v < nv; v += kTileHistThreads) {
+            const u32x4 q = __builtin_nontemporal_load(&gv[v]);
+            K k[VK];
+            __builtin_memcpy(k, &q, 16);
+            // step index of element e is first + e (negative in a head vector)
+            const int64_t first = ((int64_t)(v0 + 16ull * v) - (int64_t)b0) / (int64_t)sizeof(K);
+            const bool whole = first >= 0 && first + VK <= (int64_t)cnt &&
+                               (uint64_t)first / T == (uint64_t)(first + VK - 1) / T;
+            bool same = whole;
+#pragma unroll
+            for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
+            // one add for a whole wave holding one key value inside one tile
+            const uint64_t active = ballot(true);
+            const uint64_t kw = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)k[0] >> 32)) << 32) |
+                                __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)k[0]);
+            const uint32_t set0 = whole ? (uint32_t)((uint64_t)first / T) : 0xFFFFFFFFu;
+            const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
+            if (ballot(same && (uint64_t)k[0] == kw && set0 == setw) == active) {
+                if (lanes_below(active) == 0) {
+                    const uint32_t c = (uint32_t)VK * popc64(active);
+                    const uint32_t d = digit_of<uint64_t>(kw, shift);
+                    atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
+                    if constexpr (FIRST) {
+#pragma unroll
+                        for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<uint64_t>(kw, 8 * j)], c);
+                    }
+                }
+                continue;
+            }
+            // otherwise one add per run of equal (tile, digit) inside the lane
+            uint32_t len = 0, prev = 0;  // prev = set * 256 + digit
+#pragma unroll
+            for (int e = 0; e < VK; ++e) {
+                const int64_t idx = first + e;
+                const bool valid = idx >= 0 && idx < (int64_t)cnt;
+                const uint32_t cur = valid ? (uint32_t)((uint64_t)idx / T) * kRadix + digit_of<K>(k[e], shift) : 0;
+                if (len && (!valid || cur != prev)) {
+                    atomicAdd(&s_t[par][prev >> 8][copy][(prev & 255) >> 1], len << ((prev & 1) * 16));
+                    len = 0;
+                }
+                if (valid) {
+                    len = (len && cur == prev) ? len + 1 : 1;
+                    prev = cur;
+                    if constexpr (FIRST) {
+#pragma unroll
+                        for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
+                    }
+                }
+            }
+            if (len) atomicAdd(&s_t[par][prev >> 8][copy][(prev & 255) >> 1], len << ((prev & 1) * 16));
+        }
+        __syncthreads();
+        // each counter word has one reader, which also clears it for the
+        // step after next (the next step counts into the other parity)
+        if (tid < SETW) {
+            const uint32_t w = tid;
+            for (uint64_t t = t0; t < hi_t; ++t) {
+                const uint32_t set = (uint32_t)(t - t0);
+                uint32_t c = 0;
+#pragma unroll
+                for (int i = 0; i < kHistCopies; ++i) {
+                    c += s_t[par][set][i][w];  // halves cannot carry: each is at most T < 2^16
+                    s_t[par][set][i][w] = 0;
+                }
+                a.th[t * SETW + w] = run_lo | (run_hi << 16);
+                run_lo += c & 0xFFFFu;
+                run_hi += c >> 16;
+                tot_lo += c & 0xFFFFu;
+                tot_hi += c >> 16;
+                if ((t + 1) % a.block_tiles == 0 || t + 1 == a.tiles) {
+                    uint32_t* bs = a.bsum + (t / a.block_tiles) * kRadix;
+                    bs[2 * w] = run_lo;
+                    bs[2 * w + 1] = run_hi;
+                    run_lo = run_hi = 0;
+                }
+            }
+        }
+    }
+    if constexpr (FIRST) {
+        __syncthreads();
+        uint32_t* dst = a.part + (uint64_t)blockIdx.x * D * kRadix;
+        if (tid < SETW) {
+            dst[2 * tid] = tot_lo;
+            dst[2 * tid + 1] = tot_hi;
+        }
+        for (int i = tid; i < (D - 1) * kRadix; i += kTileHistThreads) dst[kRadix + i] = (&s_all[1][0])[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: the other two offset levels.  A super-block is 256 blocks, so its
+// prefixes stay below 2^24.
+//   bsum[b][d]  <- counts of d in the blocks of b's super-block before b
+//                  (in place); ssum[s][d] <- super-block total
+//   sbase[s][d] <- start of d in the pass output + counts of d in all
+//                  super-blocks before s
+// The output position of tile t's first key of digit d is then
+//   sbase[s][d] + bsum[b][d] + th[t][d].
+// One thread per digit value; loads are batched so the in-place update does
+// not serialise them.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kRadix) void k_block_rel(TiledArgs a, int pass) {
+    if (!a.plan[4 * pass]) return;
+    const uint64_t sb = blockIdx.x;
+    const uint32_t d = threadIdx.x;
+    const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
+    const uint64_t b0 = sb * kSuperBlock;
+    const uint64_t b1 = b0 + kSuperBlock < blocks ? b0 + kSuperBlock : blocks;
+    constexpr int kBatch = 16;
+    uint32_t run = 0;
+    for (uint64_t b = b0; b < b1; b += kBatch) {
+        uint32_t c[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) c[i] = b + i < b1 ? a.bsum[(b + i) * kRadix + d] : 0;
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            if (b + i < b1) a.bsum[(b + i) * kRadix + d] = run;
+            run += c[i];
+        }
+    }
+    a.ssum[sb * kRadix + d] = run;
+}
+
+__global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
+    if (!a.plan[4 * pass]) return;
+    const uint32_t d = threadIdx.x;
+    const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
+    const uint64_t supers = (blocks + kSuperBlock - 1) / kSuperBlock;
+    uint64_t run = a.base[(uint64_t)pass * 2 * kRadix + d];
+    for (uint64_t sb = 0; sb < supers; ++sb) {
+        a.sbase[sb * kRadix + d] = run;
+        run += a.ssum[sb * kRadix + d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 3: scatter.  Tile slot i (input order) of wave w, item k, lane l is
+// i = w*64*ITEMS + k*64 + l, so a wave's items cover a contiguous stretch in
+// input order and the per-wave ranks (wave_rank) are stable.
+//
+// The loop is software-pipelined: the next tile's keys, payloads, offsets
+// and ticket are requested right after the first barrier and consumed at
+// the top of the next iteration.  Every global load and store in the loop is
+// issued unconditionally (out-of-range lanes load a valid address and store
+// to the workspace's sink word), so the number of memory operations between
+// a request and its use is fixed and the wait at the top of the loop leaves
+// the previous tile's stores in flight.
+// ---------------------------------------------------------------------------
+template <typename K, typename V, int THREADS, int ITEMS, bool LATE>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_tile_scatter(TiledArgs a, int pass) {
+    constexpr int W = THREADS / kWave;
+    constexpr int T = THREADS * ITEMS;
+    constexpr int VK = 16 / sizeof(K);
+    constexpr int NV = T / VK + 1;                   // aligned vectors covering any tile
+    constexpr int R = (NV + THREADS - 1) / THREADS;  // vectors per thread
+    constexpr bool kHasVals = !std::is_same<V, NoVal>::value;
+    using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
+    static_assert(THREADS >= kRadix, "one thread per digit value");
+    static_assert(T < 65536, "tile counts are 16-bit");
+    constexpr bool kLateVals = LATE;
+
+    __shared__ uint64_t s_peers[W][kRadix];
+    __shared__ uint32_t s_wcnt[W][kRadix];
+    __shared__ uint64_t s_dst[kRadix];  // output position of staged slot q is s_dst[d] + q
+    __shared__ uint64_t s_wsum[4];
+    __shared__ uint32_t s_next;
+    __shared__ __attribute__((aligned(16))) K s_keys[NV * VK];  // slot T: sink of a bad rank
+    __shared__ VS s_vals[kHasVals ? T + 1 : 1];
+
+    if (!a.plan[4 * pass]) return;
+    const uint32_t src_sel = a.plan[4 * pass + 1], dst_sel = a.plan[4 * pass + 2];
+    const K* src_k = pass_source<K>(a, src_sel);
+    K* dst_k = static_cast<K*>(dst_sel == kBufOut ? a.out_k : a.tmp_k);
+    const VS* src_v = nullptr;
+    VS* dst_v = nullptr;
+    if constexpr (kHasVals) {
+        src_v = static_cast<const VS*>(src_sel == kBufIn ? a.in_v : src_sel == kBufOut ? a.out_v : a.tmp_v);
+        dst_v = static_cast<VS*>(dst_sel == kBufOut ? a.out_v : a.tmp_v);
+    }
+    K* sink_k = reinterpret_cast<K*>(a.sink);
+    VS* sink_v = reinterpret_cast<VS*>(a.sink);
+    const int shift = 8 * pass;
+
+    // contiguous tile group of this workgroup's XCD; its workgroups take the
+    // group's tiles in order from a ticket counter, so the tiles in flight
+    // on the XCD stay consecutive whatever the speed of each workgroup
+    const uint32_t groups = (gridDim.x % kXcds == 0) ? kXcds : 1u;
+    const uint32_t x = blockIdx.x % groups;
+    const uint64_t tlo = a.tiles * x / groups, thi = a.tiles * (x + 1) / groups;
+    // the counter's address is made opaque to the compiler so that the
+    // ticket request stays a plain returning atomic whose result is waited
+    // for where it is used, one tile later
+    uint32_t opaque = 0;
+    asm volatile("" : "+v"(opaque));
+    uint32_t* ctr = a.tickets + ((uint64_t)pass * kXcds + x) * kTicketStride + opaque;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < W * kRadix; i += THREADS) (&s_peers[0][0])[i] = 0;
+    const uint32_t wbase = (uint32_t)wave * kWave * ITEMS;
+    const uint32_t dig = (uint32_t)tid & (kRadix - 1);
+    const uint16_t* th16 = reinterpret_cast<const uint16_t*>(a.th);
+    const uint32_t head = (uint32_t)((reinterpret_cast<uintptr_t>(src_k) & 15) / sizeof(K));
+
+    // tile t's keys [tb, tb + cnt) lie in the aligned vectors starting at
+    // key index tb - sh, sh = (tb + head) mod VK
+    u32x4 nkv[R];
+    VS nval[ITEMS];
+    uint64_t nsb = 0;
+    uint32_t nbo = 0, nto = 0;
+    auto fetch_keys = [&](uint64_t t) {
+        const uint64_t tb = t * T;
+        const uint32_t cnt = (uint32_t)((a.n - tb) < (uint64_t)T ? (a.n - tb) : T);
+        const uint32_t sh = (uint32_t)((tb + head) % VK);
+        const uint32_t nv = (sh + cnt + VK - 1) / VK;
+        const u32x4* gv = reinterpret_cast<const u32x4*>(src_k + (tb - sh));
+        const uint64_t b = t / a.block_tiles, sb = b / kSuperBlock;
+        nsb = a.sbase[sb * kRadix + dig];
+        nbo = a.bsum[b * kRadix + dig];
+        nto = th16[t * kRadix + dig];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t v = tid + r * THREADS;
+            nkv[r] = __builtin_nontemporal_load(&gv[v < nv ? v : nv - 1]);
+        }
+    };
+    auto fetch_vals = [&](uint64_t t) {
+        if constexpr (kHasVals) {
+            const uint64_t tb = t * T;
+            const uint32_t cnt = (uint32_t)((a.n - tb) < (uint64_t)T ? (a.n - tb) : T);
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * kWave + lane;
+                nval[k] = __builtin_nontemporal_load(&src_v[tb + (idx < cnt ? idx : cnt - 1)]);
+            }
+        }
+    };
+
+    uint32_t ticket = 0;
+    if (tid == 0) s_next = atomicAdd(ctr, 1u);
+    __syncthreads();
+    uint64_t t = tlo + s_next;
+    bool bad_rank = false, bad_dst = false;
+    if (t < thi) {
+        if (tid == 0) ticket = atomicAdd(ctr, 1u);
+        fetch_keys(t);
+        fetch_vals(t);
+        // drain the first requests here, so that at the top of the loop only
+        // the previous tile's stores can be outstanding (vmcnt(0))
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();  // s_next read by all before it is rewritten
+        for (;;) {
+            const uint64_t tb = t * T;
+            const uint32_t count = (uint32_t)((a.n - tb) < (uint64_t)T ? (a.n - tb) : T);
+            const uint32_t sh = (uint32_t)((tb + head) % VK);  // tile key i sits at s_keys[i + sh]
+            const uint32_t nv = (sh + count + VK - 1) / VK;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t v = tid + r * THREADS;
+                if (v < nv) reinterpret_cast<u32x4*>(s_keys)[v] = nkv[r];
+            }
+            // payloads of this tile: copied out of the prefetch registers,
+            // or (kLateVals) used from them directly, the next tile's
+            // payloads being requested only after staging
+            VS val[ITEMS];
+            if constexpr (kHasVals && !kLateVals) {
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) val[k] = nval[k];
+            }
+            const uint64_t off = nsb + nbo + nto;
+            if (tid == 0) s_next = ticket;
+#pragma unroll
+            for (int i = 0; i < kRadix / kWave; ++i) s_wcnt[wave][lane + kWave * i] = 0;
+            __syncthreads();
+            const uint64_t tn = tlo + s_next;
+            const bool more = tn < thi;
+            if (tid == 0) ticket = atomicAdd(ctr, 1u);
+            fetch_keys(more ? tn : t);  // the last fetch repeats this tile and is not used
+            if constexpr (!kLateVals) fetch_vals(more ? tn : t);
+
+            // 16-bit keys share a register with their rank (rank < T < 2^16)
+            constexpr bool kPack = sizeof(K) == 2;
+            K key[kPack ? 1 : ITEMS];
+            uint32_t kr[ITEMS];  // kPack: key | rank << 16; otherwise the rank
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * kWave + lane;
+                const K kk = idx < count ? s_keys[idx + sh] : (K)0;
+                if constexpr (kPack) kr[k] = kk;
+                else key[k] = kk;
+            }
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const bool valid = wbase + k * kWave + lane < count;
+                const K kk = kPack ? (K)kr[k] : key[kPack ? 0 : k];
+                const uint32_t r = wave_rank(digit_of<K>(kk, shift), valid, s_peers[wave], s_wcnt[wave]);
+                if constexpr (kPack) kr[k] |= r << 16;
+                else kr[k] = r;
+            }
+            __syncthreads();
+
+            // tile histogram from the wave counts, its exclusive scan, and
+            // the per-wave bases of every digit
+            uint32_t h = 0;
+            if (tid < kRadix) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) h += s_wcnt[w][tid];
+            }
+            uint64_t total;
+            const uint32_t start = (uint32_t)scan256_exclusive<uint64_t>(tid < kRadix ? h : 0, s_wsum, &total);
+            if (tid < kRadix) {
+                uint32_t run = start;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const uint32_t c = s_wcnt[w][tid];
+                    s_wcnt[w][tid] = run;
+                    run += c;
+                }
+                s_dst[tid] = off - start;
+            }
+            __syncthreads();
+
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                if (wbase + k * kWave + lane < count) {
+                    const K kk = kPack ? (K)(kr[k] & 0xFFFFu) : key[kPack ? 0 : k];
+                    const uint32_t r = kPack ? kr[k] >> 16 : kr[k];
+                    const uint32_t pos = s_wcnt[wave][digit_of<K>(kk, shift)] + r;
+                    bad_rank |= pos >= (uint32_t)T;
+                    const uint32_t p = pos < (uint32_t)T ? pos : (uint32_t)T;
+                    s_keys[p] = kk;
+                    if constexpr (kHasVals) s_vals[p] = kLateVals ? nval[k] : val[k];
+                }
+            }
+            if constexpr (kLateVals) fetch_vals(more ? tn : t);
+            __syncthreads();
+
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t q = k * THREADS + tid;
+                const bool in = q < count;
+                const uint32_t qq = in ? q : 0u;
+                const K kk = s_keys[qq];
+                const uint64_t dst = s_dst[digit_of<K>(kk, shift)] + qq;
+                const bool ok = in && dst < a.n;
+                bad_dst |= in && !(dst < a.n);
+                *(ok ? dst_k + dst : sink_k) = kk;
+                if constexpr (kHasVals) *(ok ? dst_v + dst : sink_v) = s_vals[qq];
+                // keep the compiler from hoisting every slot's loads at once
+                if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            if (!more) break;
+            t = tn;
+        }
+    }
+    if (bad_rank) atomicOr(a.err, 4u);
+    if (bad_dst) atomicOr(a.err, 8u);
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes and launchers
+// ---------------------------------------------------------------------------
+#define FS_TILED_SHAPES(X)                 \
+    X(uint16_t, uint32_t, 512, 8, false)   \
+    X(uint16_t, uint64_t, 512, 8, false)   \
+    X(uint32_t, NoVal, 512, 8, false)      \
+    X(uint32_t, uint32_t, 512, 8, false)   \
+    X(uint32_t, uint64_t, 512, 8, false)   \
+    X(uint64_t, NoVal, 512, 8, false)      \
+    X(uint64_t, uint32_t, 512, 8, false)   \
+    X(uint64_t, uint64_t, 512, 4, false)
+
+template <typename V>
+constexpr int val_size() {
+    if constexpr (std::is_same<V, NoVal>::value) return 0;
+    else return (int)sizeof(V);
+}
+
+ScatterShape tiled_shape(int key_bytes, int val_bytes) {
+#define FS_SHAPE(K, V, THR, IT, LATE) \
+    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>()) return ScatterShape{THR, IT};
+    FS_TILED_SHAPES(FS_SHAPE)
+#undef FS_SHAPE
+    return ScatterShape{0, 0};
+}
+
+int tiled_scatter_per_cu(int key_bytes, int val_bytes) {
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define FS_OCC(K, V, THR, IT, LATE)                                                                  \
+    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>())                                   \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE>, THR, 0);
+    FS_TILED_SHAPES(FS_OCC)
+#undef FS_OCC
+    return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
+}
+
+hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
+    const bool first = pass == 0;
+    switch (key_bytes) {
+    case 2:
+        if (first) k_tile_hist<uint16_t, true><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+        else k_tile_hist<uint16_t, false><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+        break;
+    case 4:
+        if (first) k_tile_hist<uint32_t, true><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+        else k_tile_hist<uint32_t, false><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+        break;
+    case 8:
+        if (first) k_tile_hist<uint64_t, true><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+        else k_tile_hist<uint64_t, false><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s) {
+    const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
+    const uint64_t supers = (blocks + kSuperBlock - 1) / kSuperBlock;
+    k_block_rel<<<(uint32_t)supers, kRadix, 0, s>>>(a, pass);
+    k_super_base<<<1, kRadix, 0, s>>>(a, pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
+                               hipStream_t s) {
+#define FS_LAUNCH_SHAPE(K, V, THR, IT, LATE)                                  \
+    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>()) {          \
+        k_tile_scatter<K, V, THR, IT, LATE><<<groups, THR, 0, s>>>(a, pass);  \
+        return hipGetLastError();                                         \
+    }
+    FS_TILED_SHAPES(FS_LAUNCH_SHAPE)
+#undef FS_LAUNCH_SHAPE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fs
