@@ -183,7 +183,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         a.err = err;
         FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
         FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
-        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan8(part, L.hist_groups, L.digits, n, hist, base, plan, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s));
         for (int j = 0; j < L.digits; ++j) {
             if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
             FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));

@@ -161,6 +161,8 @@ ScatterShape tiled_shape(int key_bytes, int val_bytes);
 int tiled_scatter_per_cu(int key_bytes, int val_bytes);
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s);
 hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s);
+hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
+                            uint64_t* base, uint32_t* plan, hipStream_t s);
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
                                hipStream_t s);
 

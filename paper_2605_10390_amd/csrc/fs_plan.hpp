@@ -9,8 +9,9 @@ namespace fs {
 // block starts in the pass output) and whether the digit is trivial (one
 // bin holds every key, so its stable scatter is the identity and the pass is
 // skipped).  Active passes ping-pong between the output and the temporary
-// buffer so that the last one lands in the output.  256 threads, thread b
-// owns bin b; h[j] is this thread's count of digit j.
+// buffer so that the last one lands in the output.  At least 256 threads
+// (all of the block call it); thread b < 256 owns bin b and h[j] is its
+// count of digit j.
 // ----------------------------------------------------------------------------
 __device__ inline void finish_plan(const uint64_t* h, int digits, uint64_t n, uint64_t* hist,
                             uint64_t* base, uint32_t* plan) {
@@ -19,10 +20,12 @@ __device__ inline void finish_plan(const uint64_t* h, int digits, uint64_t n, ui
     const int b = threadIdx.x;
     for (int j = 0; j < digits; ++j) {
         uint64_t total;
-        const uint64_t start = scan256_exclusive<uint64_t>(h[j], wsum, &total);
-        hist[j * kRadix + b] = h[j];
-        base[(uint64_t)j * 2 * kRadix + b] = start;  // buffer 0 of pass j
-        const int any = __syncthreads_or(h[j] == n);
+        const uint64_t start = scan256_exclusive<uint64_t>(b < kRadix ? h[j] : 0, wsum, &total);
+        if (b < kRadix) {
+            hist[j * kRadix + b] = h[j];
+            base[(uint64_t)j * 2 * kRadix + b] = start;  // buffer 0 of pass j
+        }
+        const int any = __syncthreads_or(b < kRadix && h[j] == n);
         if (b == 0) trivial[j] = any;
     }
     __syncthreads();

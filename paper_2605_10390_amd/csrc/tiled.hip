@@ -26,6 +26,7 @@
 // precomputed, so results do not depend on where a workgroup runs.
 #include "fs_device.hpp"
 #include "fs_internal.hpp"
+#include "fs_plan.hpp"
 
 #include <type_traits>
 
@@ -42,8 +43,8 @@ __device__ __forceinline__ const K* pass_source(const TiledArgs& a, uint32_t sel
 // Step 1: tile histograms and the first offset level.
 //
 // A block is 65536 / T consecutive tiles; every histogram workgroup owns a
-// contiguous run of whole blocks and walks it in order, kHistTilesPer tiles
-// per step.  The counts of a tile are kept in LDS as packed 16-bit counters
+// contiguous run of whole blocks and walks it in order, a few tiles per
+// step (all of a step's loads are issued before its counting).  The counts of a tile are kept in LDS as packed 16-bit counters
 // (bins 2w and 2w+1 in word w; a tile holds at most T < 2^16 keys, so the
 // halves cannot carry), one copy per wave parity and tile of the step, and
 // double-buffered between steps so that one barrier per step suffices.
@@ -54,16 +55,18 @@ __device__ __forceinline__ const K* pass_source(const TiledArgs& a, uint32_t sel
 // With FIRST the workgroup also counts every other digit of its keys, and
 // part[g][j][b] receives its totals of digit j == b for the pass plan.
 // ---------------------------------------------------------------------------
-constexpr int kHistTilesPer = 4;
 constexpr int kHistCopies = 2;
+constexpr int kHistVecs = 4;  // 16-byte vectors per thread and step (plus one for misalignment)
 
-template <typename K, bool FIRST>
+template <typename K, bool FIRST, int TILE>
 __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int pass) {
     constexpr int D = sizeof(K);
     constexpr int VK = 16 / sizeof(K);
     constexpr int DX = FIRST ? D : 1;  // digits counted per workgroup (index 0 unused)
     constexpr int SETW = kRadix / 2;   // words of one packed tile histogram
-    __shared__ uint32_t s_t[2][kHistTilesPer][kHistCopies][SETW];
+    constexpr int TPS = kHistVecs * kTileHistThreads * VK / TILE;  // tiles per step
+    static_assert(TPS >= 1 && TPS * TILE == kHistVecs * kTileHistThreads * VK, "whole tiles per step");
+    __shared__ uint32_t s_t[2][TPS][kHistCopies][SETW];
     __shared__ uint32_t s_all[DX][kRadix];
 
     const K* src;
@@ -75,82 +78,84 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
     }
     const int shift = 8 * pass;
     const int tid = threadIdx.x, wave = tid >> 6, copy = wave % kHistCopies;
-    for (int i = tid; i < 2 * kHistTilesPer * kHistCopies * SETW; i += kTileHistThreads) (&s_t[0][0][0][0])[i] = 0;
+    for (int i = tid; i < 2 * TPS * kHistCopies * SETW; i += kTileHistThreads) (&s_t[0][0][0][0])[i] = 0;
     for (int i = tid; i < DX * kRadix; i += kTileHistThreads) (&s_all[0][0])[i] = 0;
 
     const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
     const uint64_t blo = blocks * blockIdx.x / gridDim.x, bhi = blocks * (blockIdx.x + 1) / gridDim.x;
     const uint64_t tlo = blo * a.block_tiles;
     const uint64_t thi = bhi * a.block_tiles < a.tiles ? bhi * a.block_tiles : a.tiles;
-    const uint64_t T = a.tile;
-    const uintptr_t base_addr = reinterpret_cast<uintptr_t>(src);
+    const uint32_t head = (uint32_t)((reinterpret_cast<uintptr_t>(src) & 15) / sizeof(K));
 
     // thread w < 128 owns bins 2w and 2w+1: running counts inside the
     // current block and workgroup totals
     uint32_t run_lo = 0, run_hi = 0, tot_lo = 0, tot_hi = 0;
     int par = 0;
     __syncthreads();
-    for (uint64_t t0 = tlo; t0 < thi; t0 += kHistTilesPer, par ^= 1) {
-        const uint64_t lo = t0 * T;
-        const uint64_t hi_t = t0 + kHistTilesPer < thi ? t0 + kHistTilesPer : thi;
-        const uint64_t hi = hi_t * T < a.n ? hi_t * T : a.n;
+    for (uint64_t t0 = tlo; t0 < thi; t0 += TPS, par ^= 1) {
+        const uint64_t lo = t0 * TILE;
+        const uint64_t hi_t = t0 + TPS < thi ? t0 + TPS : thi;
+        const uint64_t hi = hi_t * TILE < a.n ? hi_t * TILE : a.n;
         const uint32_t cnt = (uint32_t)(hi - lo);
-        const uintptr_t b0 = base_addr + lo * sizeof(K), b1 = base_addr + hi * sizeof(K);
-        const uintptr_t v0 = b0 & ~(uintptr_t)15;
-        const uint32_t nv = (uint32_t)((((b1 + 15) & ~(uintptr_t)15) - v0) / 16);
-        // derived from src (not from the integer address) so that the
-        // compiler keeps these global-memory loads
-        const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - (b0 - v0) / sizeof(K)));
-        for (uint32_t v = tid; v < nv; v += kTileHistThreads) {
-            const u32x4 q = __builtin_nontemporal_load(&gv[v]);
-            K k[VK];
-            __builtin_memcpy(k, &q, 16);
-            // step index of element e is first + e (negative in a head vector)
-            const int64_t first = ((int64_t)(v0 + 16ull * v) - (int64_t)b0) / (int64_t)sizeof(K);
-            const bool whole = first >= 0 && first + VK <= (int64_t)cnt &&
-                               (uint64_t)first / T == (uint64_t)(first + VK - 1) / T;
-            bool same = whole;
+        // the step's keys [lo, hi) lie in the aligned vectors starting at key
+        // index lo - sh
+        const uint32_t sh = (uint32_t)((lo + head) % VK);
+        const uint32_t nv = (sh + cnt + VK - 1) / VK;
+        const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - sh));
+        // all of the step's loads first, then the counting
+        u32x4 q[kHistVecs + 1];
 #pragma unroll
-            for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
-            // one add for a whole wave holding one key value inside one tile
-            const uint64_t active = ballot(true);
-            const uint64_t kw = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)k[0] >> 32)) << 32) |
-                                __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)k[0]);
-            const uint32_t set0 = whole ? (uint32_t)((uint64_t)first / T) : 0xFFFFFFFFu;
-            const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
-            if (ballot(same && (uint64_t)k[0] == kw && set0 == setw) == active) {
-                if (lanes_below(active) == 0) {
-                    const uint32_t c = (uint32_t)VK * popc64(active);
-                    const uint32_t d = digit_of<uint64_t>(kw, shift);
-                    atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
-                    if constexpr (FIRST) {
+        for (int r = 0; r <= kHistVecs; ++r) {
+            const uint32_t v = tid + r * kTileHistThreads;
+            if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
+        }
 #pragma unroll
-                        for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<uint64_t>(kw, 8 * j)], c);
+        for (int r = 0; r <= kHistVecs; ++r) {
+            const uint32_t v = tid + r * kTileHistThreads;
+            if (r == kHistVecs && __builtin_amdgcn_readfirstlane(v) >= nv) break;  // wave-uniform
+            if (v < nv) {
+                K k[VK];
+                __builtin_memcpy(k, &q[r], 16);
+                // step index of element e is first + e (negative in a head vector)
+                const int32_t first = (int32_t)(v * VK) - (int32_t)sh;
+                const bool whole = first >= 0 && first + VK <= (int32_t)cnt &&
+                                   (uint32_t)first / TILE == (uint32_t)(first + VK - 1) / TILE;
+                bool same = whole;
+#pragma unroll
+                for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
+                // one add for a whole wave holding one key value inside one tile
+                const uint64_t active = ballot(true);
+                const uint64_t kw =
+                    ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)k[0] >> 32)) << 32) |
+                    __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)k[0]);
+                const uint32_t set0 = whole ? (uint32_t)first / TILE : 0xFFFFFFFFu;
+                const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
+                if (ballot(same && (uint64_t)k[0] == kw && set0 == setw) == active) {
+                    if (lanes_below(active) == 0) {
+                        const uint32_t c = (uint32_t)VK * popc64(active);
+                        const uint32_t d = digit_of<uint64_t>(kw, shift);
+                        atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
+                        if constexpr (FIRST) {
+#pragma unroll
+                            for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<uint64_t>(kw, 8 * j)], c);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const int32_t idx = first + e;
+                        if (idx >= 0 && idx < (int32_t)cnt) {
+                            const uint32_t d = digit_of<K>(k[e], shift);
+                            atomicAdd(&s_t[par][(uint32_t)idx / TILE][copy][d >> 1], 1u << ((d & 1) * 16));
+                            if constexpr (FIRST) {
+#pragma unroll
+                                for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
+                            }
+                        }
                     }
                 }
-                continue;
             }
-            // otherwise one add per run of equal (tile, digit) inside the lane
-            uint32_t len = 0, prev = 0;  // prev = set * 256 + digit
-#pragma unroll
-            for (int e = 0; e < VK; ++e) {
-                const int64_t idx = first + e;
-                const bool valid = idx >= 0 && idx < (int64_t)cnt;
-                const uint32_t cur = valid ? (uint32_t)((uint64_t)idx / T) * kRadix + digit_of<K>(k[e], shift) : 0;
-                if (len && (!valid || cur != prev)) {
-                    atomicAdd(&s_t[par][prev >> 8][copy][(prev & 255) >> 1], len << ((prev & 1) * 16));
-                    len = 0;
-                }
-                if (valid) {
-                    len = (len && cur == prev) ? len + 1 : 1;
-                    prev = cur;
-                    if constexpr (FIRST) {
-#pragma unroll
-                        for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
-                    }
-                }
-            }
-            if (len) atomicAdd(&s_t[par][prev >> 8][copy][(prev & 255) >> 1], len << ((prev & 1) * 16));
+            __builtin_amdgcn_sched_barrier(0);  // count one vector at a time (register pressure)
         }
         __syncthreads();
         // each counter word has one reader, which also clears it for the
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
                 uint32_t c = 0;
 #pragma unroll
                 for (int i = 0; i < kHistCopies; ++i) {
-                    c += s_t[par][set][i][w];  // halves cannot carry: each is at most T < 2^16
+                    c += s_t[par][set][i][w];  // halves cannot carry: each is at most TILE < 2^16
                     s_t[par][set][i][w] = 0;
                 }
                 a.th[t * SETW + w] = run_lo | (run_hi << 16);
@@ -188,6 +193,52 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         }
         for (int i = tid; i < (D - 1) * kRadix; i += kTileHistThreads) dst[kRadix + i] = (&s_all[1][0])[i];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Pass plan from the first pass's workgroup totals: every digit's global
+// counts, their exclusive scans and the trivial digits (finish_plan).  One
+// block of kPlanThreads; each group of 256 threads sums a share of the
+// workgroups, with independent loads in flight.
+// ---------------------------------------------------------------------------
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void k_tile_plan(const uint32_t* __restrict__ part, uint32_t groups,
+                                                            int digits, uint64_t n, uint64_t* hist,
+                                                            uint64_t* base, uint32_t* plan) {
+    constexpr int Q = kPlanThreads / kRadix;
+    __shared__ uint64_t s_h[Q][kRadix];
+    const int tid = threadIdx.x, b = tid % kRadix, q = tid / kRadix;
+    uint64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < digits; ++j) {
+        uint64_t acc = 0;
+        constexpr int kBatch = 8;
+        for (uint32_t g0 = q; g0 < groups; g0 += Q * kBatch) {
+            uint32_t v[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                const uint32_t g = g0 + i * Q;
+                v[i] = g < groups ? part[((uint64_t)g * digits + j) * kRadix + b] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) acc += v[i];
+        }
+        s_h[q][b] = acc;
+        __syncthreads();
+        if (q == 0) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i) acc += s_h[i][b];
+            h[j] = acc;
+        }
+        __syncthreads();
+    }
+    finish_plan(h, digits, n, hist, base, plan);
+}
+
+hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
+                            uint64_t* base, uint32_t* plan, hipStream_t s) {
+    k_tile_plan<<<1, kPlanThreads, 0, s>>>(part, groups, digits, n, hist, base, plan);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -499,23 +550,18 @@ int tiled_scatter_per_cu(int key_bytes, int val_bytes) {
     return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
 }
 
+template <typename K, int TILE>
+static void launch_hist_t(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
+    if (pass == 0) k_tile_hist<K, true, TILE><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+    else k_tile_hist<K, false, TILE><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+}
+
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
-    const bool first = pass == 0;
-    switch (key_bytes) {
-    case 2:
-        if (first) k_tile_hist<uint16_t, true><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-        else k_tile_hist<uint16_t, false><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-        break;
-    case 4:
-        if (first) k_tile_hist<uint32_t, true><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-        else k_tile_hist<uint32_t, false><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-        break;
-    case 8:
-        if (first) k_tile_hist<uint64_t, true><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-        else k_tile_hist<uint64_t, false><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-        break;
-    default: return hipErrorInvalidValue;
-    }
+    if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, groups, s);
+    else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, groups, s);
+    else if (key_bytes == 8 && a.tile == 4096) launch_hist_t<uint64_t, 4096>(a, pass, groups, s);
+    else if (key_bytes == 8 && a.tile == 2048) launch_hist_t<uint64_t, 2048>(a, pass, groups, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
