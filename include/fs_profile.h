@@ -23,7 +23,7 @@ extern "C" {
 typedef enum {
     FS_KERNEL_HISTOGRAM = 0, /* per-workgroup digit histograms (one read of the keys) */
     FS_KERNEL_PLAN = 1,      /* merge of histograms, prefix scans, pass plan */
-    FS_KERNEL_SCATTER = 2,   /* one stable scatter pass over a portion of the keys */
+    FS_KERNEL_SCATTER = 2,   /* one stable scatter pass over all keys */
     FS_KERNEL_EXPAND = 3,    /* 16-bit keys-only output written from the histogram */
     FS_KERNEL_AUX = 4,       /* clears and the copy of an all-trivial sort */
     FS_KERNEL_SEGMENTED = 5, /* batched segmented-sort kernels */

@@ -26,15 +26,6 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
     L.val_bytes = val_bytes;
     L.digits = key_bytes;  // 8-bit digits
     L.expand16 = key_bytes == 2 && val_bytes == 0;
-    L.compressed16 = key_bytes == 2;
-    if (L.compressed16)
-        L.hist_groups = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), num_cus);
-    else
-        L.hist_groups = (uint32_t)std::min<uint64_t>(
-            std::max<uint64_t>(ceil_div(n, (uint64_t)kHist8Threads * 16), 1), 2ull * num_cus);
-    const uint64_t T = scatter_shape(key_bytes, val_bytes).tile();
-    L.portions = (uint32_t)std::max<uint64_t>(ceil_div(n, kPortionKeys), 1);
-    L.tiles_per_portion = (uint32_t)std::max<uint64_t>(ceil_div(std::min<uint64_t>(n, kPortionKeys), T), 1);
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -42,21 +33,18 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
         off = align_up(off + std::max<size_t>(bytes, 1), 256);
         return o;
     };
-    L.err = take(4 + 4ull * 8 * L.portions);  // error word, then one ticket per (pass, portion)
-    L.tickets = L.err + 4;
+    L.err = take(4);
     L.plan = take(4ull * kPlanWords);
     L.hist = take(8ull * 8 * kRadix);
     L.base = take(8ull * 8 * 2 * kRadix);
-    if (L.compressed16 && L.expand16) {
+    if (L.expand16) {
+        // compressed 2^16-bin histogram, its prefix, expansion
+        L.hist_groups = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), num_cus);
         L.part = take(4ull * L.hist_groups * kHist16Words);
         L.wrap = take(4ull * 2 * kHist16Words);
         L.h16 = take(8ull * 65536);
         L.p16 = take(8ull * 65537);
-    }
-    L.tiled = !L.expand16;
-    L.chunked16 = false;
-    if (L.tiled) {
-        L.compressed16 = false;
+    } else {
         L.tile = (uint32_t)tiled_shape(key_bytes, val_bytes).tile();
         L.tiles = std::max<uint64_t>(ceil_div(n, L.tile), 1);
         L.tile_blocks = ceil_div(L.tiles, 65536 / L.tile);
@@ -75,26 +63,6 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
         L.sbase = take(8ull * kRadix * L.tile_supers);
         L.tile_tickets = take(4ull * L.digits * kXcds * kTicketStride);
         L.sink = take(16);
-        L.tmp_keys = take((size_t)n * key_bytes);
-        if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
-    } else if (L.chunked16) {
-        static const int per_cu4 = range_scatter16_per_cu(4), per_cu8 = range_scatter16_per_cu(8);
-        const uint64_t resident = (uint64_t)num_cus * (val_bytes == 8 ? per_cu8 : per_cu4);
-        L.chunks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, 1u << 16), 1), resident);
-        L.ranges1 = L.chunks;
-        L.log_capacity = (uint32_t)(2 * (n >> 16) + 64);
-        L.J = take(4ull * L.chunks * 65536);
-        L.log = take(4ull + 4ull * L.log_capacity);
-        L.H = take(8ull * 65536);
-        L.RP = take(8ull * 65536);
-        L.O0 = take(8ull * (L.chunks + 1) * kRadix);
-        L.O1 = take(8ull * (L.ranges1 + 1) * kRadix);
-        L.start1 = take(8ull * (L.ranges1 + 1));
-        L.run1 = take(4ull * (L.ranges1 + 1));
-        L.tmp_keys = take((size_t)n * key_bytes);
-        L.tmp_vals = take((size_t)n * val_bytes);
-    } else if (!L.expand16) {
-        L.state = take(4ull * kRadix * L.tiles_per_portion);
         L.tmp_keys = take((size_t)n * key_bytes);
         if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
     }
@@ -148,144 +116,61 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     if (*workspace_bytes < L.total) return FS_ERR_WORKSPACE_TOO_SMALL;
     if (overlaps(workspace, L.total, keys_out, kbytes) || overlaps(workspace, L.total, keys_in, kbytes))
         return FS_ERR_INVALID_ARG;
+    if (val_bytes && (overlaps(workspace, L.total, vals_in, vbytes) || overlaps(workspace, L.total, vals_out, vbytes)))
+        return FS_ERR_INVALID_ARG;
 
     char* w = static_cast<char*>(workspace);
     uint32_t* err = reinterpret_cast<uint32_t*>(w + L.err);
-    uint32_t* tickets = reinterpret_cast<uint32_t*>(w + L.tickets);
     uint32_t* plan = reinterpret_cast<uint32_t*>(w + L.plan);
     uint64_t* hist = reinterpret_cast<uint64_t*>(w + L.hist);
     uint64_t* base = reinterpret_cast<uint64_t*>(w + L.base);
     uint32_t* part = reinterpret_cast<uint32_t*>(w + L.part);
 
-    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(err, 1 + 8ull * L.portions, 0, s));
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(err, 1, 0, s));
 
-    if (L.tiled) {
-        TiledArgs a;
-        a.in_k = keys_in;
-        a.out_k = keys_out;
-        a.tmp_k = w + L.tmp_keys;
-        a.in_v = vals_in;
-        a.out_v = vals_out;
-        a.tmp_v = val_bytes ? w + L.tmp_vals : nullptr;
-        a.n = n;
-        a.tiles = L.tiles;
-        a.tile = L.tile;
-        a.block_tiles = 65536 / L.tile;
-        a.plan = plan;
-        a.base = base;
-        a.th = reinterpret_cast<uint32_t*>(w + L.th);
-        a.bsum = reinterpret_cast<uint32_t*>(w + L.bsum);
-        a.ssum = reinterpret_cast<uint32_t*>(w + L.ssum);
-        a.sbase = reinterpret_cast<uint64_t*>(w + L.sbase);
-        a.part = part;
-        a.tickets = reinterpret_cast<uint32_t*>(w + L.tile_tickets);
-        a.sink = w + L.sink;
-        a.err = err;
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
-        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
-        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s));
-        for (int j = 0; j < L.digits; ++j) {
-            if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
-            FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
-            FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, s));
-        }
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
-        if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
-        return FS_OK;
-    }
-
-    if (L.chunked16) {
-        Plan16 p;
-        p.chunks = L.chunks;
-        p.ranges1 = L.ranges1;
-        p.J = reinterpret_cast<uint32_t*>(w + L.J);
-        p.log_count = reinterpret_cast<uint32_t*>(w + L.log);
-        p.log_entries = p.log_count + 1;
-        p.log_capacity = L.log_capacity;
-        p.H = reinterpret_cast<uint64_t*>(w + L.H);
-        p.RP = reinterpret_cast<uint64_t*>(w + L.RP);
-        p.hist = hist;
-        p.base = base;
-        p.O0 = reinterpret_cast<uint64_t*>(w + L.O0);
-        p.O1 = reinterpret_cast<uint64_t*>(w + L.O1);
-        p.start1 = reinterpret_cast<uint64_t*>(w + L.start1);
-        p.run1 = reinterpret_cast<uint32_t*>(w + L.run1);
-        p.plan = plan;
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(p.log_count, 1, 0, s));
-        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_joint16(keys_in, n, kb, 0, L.chunks, p.J, p.log_count,
-                                                         p.log_entries, p.log_capacity, s));
-        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_chunked16(p, n, s));
-        for (int j = 0; j < 2; ++j) {
-            RangeArgs a;
-            a.in_k = keys_in;
-            a.out_k = keys_out;
-            a.tmp_k = w + L.tmp_keys;
-            a.in_v = vals_in;
-            a.out_v = vals_out;
-            a.tmp_v = w + L.tmp_vals;
-            a.n = n;
-            a.ranges = j == 0 ? L.chunks : L.ranges1;
-            a.range_start = j == 0 ? nullptr : p.start1;
-            a.offsets = j == 0 ? p.O0 : p.O1;
-            a.shift = 8 * j;
-            a.pass = j;
-            a.plan = plan;
-            a.err = err;
-            FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_range_scatter16(a, a.ranges, val_bytes, s));
-        }
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
-        return FS_OK;
-    }
-
-    if (L.compressed16) {
+    if (L.expand16) {
+        // the whole key is one 16-bit digit: compressed histogram, prefix,
+        // expansion (Algorithm 5 with no trailing bits)
         uint32_t* wrap = reinterpret_cast<uint32_t*>(w + L.wrap);
         uint64_t* h16 = reinterpret_cast<uint64_t*>(w + L.h16);
+        uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
         FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
-        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups, part, wrap,
-                                                   wrap + kHist16Words, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups,
+                                                         part, wrap, wrap + kHist16Words, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part, L.hist_groups, wrap, wrap + kHist16Words, h16, s));
-        if (L.expand16) {
-            uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
-            FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
-            FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
-            return FS_OK;
-        }
-        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s));
-    } else {
-        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist8(keys_in, n, kb, L.hist_groups, part, s));
-        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan8(part, L.hist_groups, L.digits, n, hist, base, plan, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
+        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
+        return FS_OK;
     }
 
-    uint32_t* state = reinterpret_cast<uint32_t*>(w + L.state);
-    const uint64_t T = scatter_shape(kb, val_bytes).tile();
+    TiledArgs a;
+    a.in_k = keys_in;
+    a.out_k = keys_out;
+    a.tmp_k = w + L.tmp_keys;
+    a.in_v = vals_in;
+    a.out_v = vals_out;
+    a.tmp_v = val_bytes ? w + L.tmp_vals : nullptr;
+    a.n = n;
+    a.tiles = L.tiles;
+    a.tile = L.tile;
+    a.block_tiles = 65536 / L.tile;
+    a.plan = plan;
+    a.base = base;
+    a.th = reinterpret_cast<uint32_t*>(w + L.th);
+    a.bsum = reinterpret_cast<uint32_t*>(w + L.bsum);
+    a.ssum = reinterpret_cast<uint32_t*>(w + L.ssum);
+    a.sbase = reinterpret_cast<uint64_t*>(w + L.sbase);
+    a.part = part;
+    a.tickets = reinterpret_cast<uint32_t*>(w + L.tile_tickets);
+    a.sink = w + L.sink;
+    a.err = err;
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
+    FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
+    FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s));
     for (int j = 0; j < L.digits; ++j) {
-        for (uint32_t q = 0; q < L.portions; ++q) {
-            const uint64_t pb = (uint64_t)q * kPortionKeys;
-            const uint64_t plen = std::min<uint64_t>(kPortionKeys, n - pb);
-            const uint32_t tiles = (uint32_t)ceil_div(plen, T);
-            FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(state, (uint64_t)tiles * kRadix, 0, s));
-            ScatterArgs a;
-            a.in_k = keys_in;
-            a.out_k = keys_out;
-            a.tmp_k = w + L.tmp_keys;
-            a.in_v = vals_in;
-            a.out_v = vals_out;
-            a.tmp_v = val_bytes ? w + L.tmp_vals : nullptr;
-            a.n = n;
-            a.portion_begin = pb;
-            a.portion_len = plen;
-            a.tiles = tiles;
-            a.shift = 8 * j;
-            a.pass = j;
-            a.plan = plan;
-            a.base_cur = base + (uint64_t)j * 2 * kRadix + (q % 2) * kRadix;
-            a.base_next = base + (uint64_t)j * 2 * kRadix + ((q + 1) % 2) * kRadix;
-            a.state = state;
-            a.ticket = tickets + j * L.portions + q;
-            a.err = err;
-            FS_LAUNCH(FS_KERNEL_SCATTER, plen, launch_scatter(a, kb, val_bytes, s));
-        }
+        if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
+        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, s));
     }
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
     if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));

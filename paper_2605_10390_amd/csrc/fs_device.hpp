@@ -9,12 +9,6 @@ constexpr int kWave = 64;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-// Look-back state word: 2-bit flag over a 30-bit count (counts within one
-// portion stay below 2^30, see kPortionKeys).
-constexpr uint32_t kFlagAggregate = 1u << 30;
-constexpr uint32_t kFlagPrefix = 2u << 30;
-constexpr uint32_t kCountMask = (1u << 30) - 1;
-
 // Bound on look-back polls before a workgroup gives up and raises the
 // workspace error word (never reached by a correct launch; it keeps every
 // wave finite).
@@ -40,19 +34,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 }
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__builtin_popcountll(m); }
-
-// Lanes of `candidates` whose 8-bit digit equals this lane's digit: one
-// ballot per digit bit, each keeping the lanes that agree on that bit.
-__device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t candidates) {
-    uint64_t peers = candidates;
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = ballot(bit);
-        peers &= bit ? m : ~m;
-    }
-    return peers;
-}
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

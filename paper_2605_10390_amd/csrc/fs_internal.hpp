@@ -8,12 +8,6 @@
 
 namespace fs {
 
-// Keys per look-back portion of one pass.  Counts inside a portion stay
-// below 2^30, so a look-back state word holds flag + count in 32 bits;
-// portions of a pass run as consecutive launches and hand their running bin
-// bases on through the workspace.
-constexpr uint64_t kPortionKeys = 1ull << 28;
-
 // Histogram launch shapes.
 constexpr int kHist16Threads = 1024;
 constexpr int kHist16Words = 32768;  // 2^16 bins as packed 16-bit counter pairs
@@ -25,25 +19,15 @@ struct ScatterShape {
     int tile() const { return threads * items; }
 };
 
-// Tile shape of the scatter pass for a key/value width.
-ScatterShape scatter_shape(int key_bytes, int val_bytes);
-
 // Offsets (bytes) of every region of a sort's workspace.
 struct SortLayout {
     int key_bytes = 0, val_bytes = 0, digits = 0;
-    bool expand16 = false;    // 16-bit keys only: histogram + expansion
-    bool compressed16 = false;  // digit histograms from the compressed 2^16-bin histogram
-    bool chunked16 = false;     // 16-bit keys + payload: per-chunk histograms, no look-back
-    bool tiled = false;         // reduce-then-scan over fixed tiles
+    bool expand16 = false;  // 16-bit keys only: compressed histogram + expansion
+    uint32_t hist_groups = 0;  // workgroups of the histogram kernel
     uint32_t tile = 0, scatter_groups = 0;
     uint64_t tiles = 0, tile_blocks = 0, tile_supers = 0;
-    size_t th = 0, bsum = 0, ssum = 0, sbase = 0, tile_tickets = 0, sink = 0;
-    uint32_t chunks = 0, ranges1 = 0, log_capacity = 0;
-    size_t J = 0, log = 0, H = 0, RP = 0, O0 = 0, O1 = 0, start1 = 0, run1 = 0;
-    uint32_t hist_groups = 0;   // workgroups of the histogram kernel
-    uint32_t portions = 0, tiles_per_portion = 0;
-    size_t err = 0, tickets = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0,
-           p16 = 0, state = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
+    size_t err = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0, p16 = 0, th = 0, bsum = 0,
+           ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
 };
 
 SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus);
@@ -68,66 +52,6 @@ hipError_t launch_reduce8(const uint32_t* part, uint32_t groups, int digits, uin
 hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t n, hipStream_t s);
 hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
                           hipStream_t s);
-
-struct ScatterArgs {
-    const void* in_k;
-    void* out_k;
-    void* tmp_k;
-    const void* in_v;
-    void* out_v;
-    void* tmp_v;
-    uint64_t n;  // total keys (bound of every destination index)
-    uint64_t portion_begin;
-    uint64_t portion_len;
-    uint32_t tiles;
-    int shift;
-    int pass;
-    const uint32_t* plan;
-    const uint64_t* base_cur;
-    uint64_t* base_next;
-    uint32_t* state;
-    uint32_t* ticket;
-    uint32_t* err;
-};
-
-hipError_t launch_scatter(const ScatterArgs& a, int key_bytes, int val_bytes, hipStream_t s);
-
-// ---- chunked two-pass path for 16-bit keys with payloads (chunked.hip) ----
-struct RangeArgs {
-    const void* in_k;
-    void* out_k;
-    void* tmp_k;
-    const void* in_v;
-    void* out_v;
-    void* tmp_v;
-    uint64_t n;
-    uint32_t ranges;              // number of workgroups / ranges
-    const uint64_t* range_start;  // ranges+1 starts, or null: equal chunks of n
-    const uint64_t* offsets;      // [ranges][256] first output position per digit value
-    int shift;
-    int pass;
-    const uint32_t* plan;
-    uint32_t* err;
-};
-
-struct Plan16 {
-    uint32_t chunks, ranges1;
-    uint32_t* J;  // [chunks][65536] per-chunk counts, then prefixes over chunks
-    uint32_t* log_count;
-    uint32_t* log_entries;
-    uint32_t log_capacity;
-    uint64_t *H, *RP, *hist, *base, *O0, *O1, *start1;
-    uint32_t* run1;
-    uint32_t* plan;
-};
-
-uint64_t chunk_begin(uint64_t n, uint32_t chunks, uint32_t c);
-hipError_t launch_joint16(const void* keys, uint64_t n, int key_bytes, int shift, uint32_t chunks,
-                          uint32_t* J, uint32_t* log_count, uint32_t* log_entries, uint32_t capacity,
-                          hipStream_t s);
-hipError_t launch_plan_chunked16(const Plan16& p, uint64_t n, hipStream_t s);
-hipError_t launch_range_scatter16(const RangeArgs& a, uint32_t groups, int val_bytes, hipStream_t s);
-int range_scatter16_per_cu(int val_bytes);  // resident workgroups per CU
 
 // ---- tiled reduce-then-scan path (tiled.hip) -------------------------------
 constexpr uint64_t kSuperBlock = 256;  // blocks per super-block of the offset scan

@@ -559,6 +559,7 @@ static void launch_hist_t(const TiledArgs& a, int pass, uint32_t groups, hipStre
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
     if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, groups, s);
     else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, groups, s);
+    else if (key_bytes == 4 && a.tile == 2048) launch_hist_t<uint32_t, 2048>(a, pass, groups, s);
     else if (key_bytes == 8 && a.tile == 4096) launch_hist_t<uint64_t, 4096>(a, pass, groups, s);
     else if (key_bytes == 8 && a.tile == 2048) launch_hist_t<uint64_t, 2048>(a, pass, groups, s);
     else return hipErrorInvalidValue;

@@ -4,7 +4,8 @@ for byte (integer work: bit-exact, tolerance 0), on the same seeded inputs.
 Sizes span several tiles (a scatter tile is 4096 keys) with ragged tails,
 every key width and payload width, every distribution of the configs, and
 the edge cases: n = 0 and 1, unaligned buffers, all-equal keys (every digit
-trivial, the sort is a copy) and a size that crosses a look-back portion.
+trivial, the sort is a copy) and a size whose tile offsets span every level
+of the offset scan.
 """
 import numpy as np
 import pytest
@@ -152,9 +153,10 @@ def test_invalid_arguments(gpu):
         fs.sort_pairs(k, v, vals_out=v)
 
 
-def test_crosses_a_lookback_portion(gpu):
-    """n just above one look-back portion (2^28 keys): the second portion
-    starts from the running bin bases handed over by the first."""
+def test_many_offset_levels_and_ragged_tail(gpu):
+    """2^28 + 4097 keys: 65537 tiles, so every level of the tile offset scan
+    (inside blocks, inside super-blocks, over super-blocks) has several
+    entries and the last tile holds one key."""
     n = (1 << 28) + 4097
     seed = fsgen.seed_for(1, 0)
     kd = fsgen.keys_device("uniform", 16, n, seed)
