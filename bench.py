@@ -59,10 +59,21 @@ def scatter_bytes_per_key(key_bits, val_bytes):
     return 2 * (key_bits // 8 + val_bytes)
 
 
+def scatter_bytes_per_launch_key(key_bits, val_bytes, passes):
+    """Average algorithmic bytes per key of one scatter launch.  A 16-bit
+    pair sort's last pass writes only the payloads (its keys are expanded
+    from the 16-bit histogram), so it moves kb bytes per key fewer."""
+    full = scatter_bytes_per_key(key_bits, val_bytes)
+    if key_bits == 16 and val_bytes and passes:
+        return (passes * full - key_bits // 8) / passes
+    return full
+
+
 def algorithmic_bytes_per_key(key_bits, val_bytes, passes):
     """Whole sort: one read of the keys for the histograms, then every pass
     reads and writes key + payload; a 16-bit keys-only sort is one read plus
-    one write of the keys (expansion)."""
+    one write of the keys (expansion).  For 16-bit pairs the last pass's key
+    write is replaced by the expansion's: the same bytes."""
     kb = key_bits // 8
     if key_bits == 16 and val_bytes == 0:
         return 2 * kb
@@ -412,7 +423,8 @@ def main():
     for name, kinfo in kernels.items():
         if kinfo["launches"]:
             kinfo["ms_avg"] = kinfo["ms_total"] / kinfo["launches"]
-            per_key = {"histogram": key_bits // 8, "scatter": scatter_bytes_per_key(key_bits, val_bytes),
+            per_key = {"histogram": key_bits // 8,
+                       "scatter": scatter_bytes_per_launch_key(key_bits, val_bytes, passes),
                        "expand": key_bits // 8}.get(name)
             if per_key and kinfo["ms_total"] > 0:
                 kinfo["gbps"] = kinfo["keys"] * per_key / (kinfo["ms_total"] / 1e3) / 1e9
@@ -422,7 +434,7 @@ def main():
         dom_bytes_per_key = 2  # the expansion writes every key once
     else:
         dom = kernels["scatter"]
-        dom_bytes_per_key = scatter_bytes_per_key(key_bits, val_bytes)
+        dom_bytes_per_key = scatter_bytes_per_launch_key(key_bits, val_bytes, passes)
     achieved = (dom["keys"] / dom["launches"]) * dom_bytes_per_key / (dom["ms_avg"] / 1e3) / 1e9
     src_hash = kernel_source_hash()
     traffic = read_traffic(src_hash) if args.workload == "c1" else None

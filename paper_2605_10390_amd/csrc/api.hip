@@ -63,6 +63,16 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
         L.sbase = take(8ull * kRadix * L.tile_supers);
         L.tile_tickets = take(4ull * L.digits * kXcds * kTicketStride);
         L.sink = take(16);
+        L.pairs16 = key_bytes == 2;
+        if (L.pairs16) {
+            // first histogram: the compressed 2^16-bin histogram of the keys,
+            // one workgroup per CU
+            L.hist16_groups = (uint32_t)std::min<uint64_t>(L.tile_blocks, (uint64_t)num_cus);
+            L.part16 = take(4ull * L.hist16_groups * kHist16Words);
+            L.wrap = take(4ull * 2 * kHist16Words);
+            L.h16 = take(8ull * 65536);
+            L.p16 = take(8ull * 65537);
+        }
         L.tmp_keys = take((size_t)n * key_bytes);
         if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
     }
@@ -165,12 +175,36 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     a.sink = w + L.sink;
     a.err = err;
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
+    if (L.pairs16) {
+        // 16-bit keys with payloads: the first histogram is the compressed
+        // 2^16-bin histogram (plus digit-0 tile counts); the last pass moves
+        // only payloads and the sorted keys are expanded from the histogram
+        uint32_t* part16 = reinterpret_cast<uint32_t*>(w + L.part16);
+        uint32_t* wrap = reinterpret_cast<uint32_t*>(w + L.wrap);
+        uint64_t* h16 = reinterpret_cast<uint64_t*>(w + L.h16);
+        uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n,
+                  launch_tile_hist16(a, L.hist16_groups, part16, wrap, wrap + kHist16Words, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part16, L.hist16_groups, wrap, wrap + kHist16Words, h16, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
+        for (int j = 0; j < 2; ++j) {
+            if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
+            FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
+            // pass 1, when it runs, is the last pass and writes the output
+            FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, j == 1, s));
+        }
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
+        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
+        return FS_OK;
+    }
     FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
     FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s));
     for (int j = 0; j < L.digits; ++j) {
         if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
-        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, s));
+        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, false, s));
     }
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
     if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));

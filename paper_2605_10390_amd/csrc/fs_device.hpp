@@ -54,6 +54,29 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
                           : __builtin_amdgcn_ubfe((uint32_t)(key >> 32), (uint32_t)(shift - 32), kRadixBits);
 }
 
+// Compressed 2^16-bin histogram of 16-bit keys in LDS.
+//
+// Counter pair w holds bin 2w in its low half and bin 2w+1 in its high half.
+// Every increment is a returning LDS add, so the adding lane sees the old
+// word and can tell whether its add carried out of the low half (which also
+// bumped the high half by one) or out of the whole word.  Atomic adds are
+// linearised, so each wrap is seen by exactly one lane, which counts it in
+// wrap_lo[w] or wrap_word[w] (global, rare: one per 65536 keys of a bin).
+// Exact decode of the sums over all workgroups, with W_i the raw words:
+//   lo  = sum(W_i & 0xFFFF) + 2^16 * wrap_lo[w]
+//   V   = sum(W_i)          + 2^32 * wrap_word[w]     (= lo + 2^16 * hi)
+//   hi  = (V - lo) / 2^16
+__device__ __forceinline__ void hist16_add(uint32_t* cnt, uint32_t key, uint32_t c,
+                                           uint32_t* wrap_lo, uint32_t* wrap_word) {
+    const uint32_t w = key >> 1;
+    const uint32_t inc = (key & 1u) ? (c << 16) : c;
+    const uint32_t old = atomicAdd(&cnt[w], inc);
+    const bool word_wrap = (old + inc) < old;
+    const bool lo_wrap = ((old & 0xFFFFu) + (inc & 0xFFFFu)) > 0xFFFFu;
+    if (__builtin_expect(word_wrap, 0)) atomicAdd(&wrap_word[w], 1u);
+    if (__builtin_expect(lo_wrap, 0)) atomicAdd(&wrap_lo[w], 1u);
+}
+
 // Exclusive scan of one value per thread over the first 256 threads of a
 // block (4 waves); every thread of the block must call it.  `wsum` is LDS
 // scratch of at least 4 words.  Returns the exclusive prefix for threads

@@ -23,11 +23,13 @@ struct ScatterShape {
 struct SortLayout {
     int key_bytes = 0, val_bytes = 0, digits = 0;
     bool expand16 = false;  // 16-bit keys only: compressed histogram + expansion
+    bool pairs16 = false;   // 16-bit keys + payload: tiled passes, keys expanded at the end
     uint32_t hist_groups = 0;  // workgroups of the histogram kernel
+    uint32_t hist16_groups = 0;
     uint32_t tile = 0, scatter_groups = 0;
     uint64_t tiles = 0, tile_blocks = 0, tile_supers = 0;
     size_t err = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0, p16 = 0, th = 0, bsum = 0,
-           ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
+           ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, part16 = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
 };
 
 SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus);
@@ -88,7 +90,9 @@ hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s);
 hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
                             uint64_t* base, uint32_t* plan, hipStream_t s);
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
-                               hipStream_t s);
+                               bool skip_keys, hipStream_t s);
+hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
+                              uint32_t* wrap_word, hipStream_t s);
 
 // ---- per-kernel event timing (include/fs_profile.h) ------------------------
 void profile_mark(int kind, uint64_t keys, hipStream_t s, hipEvent_t* begin_out);

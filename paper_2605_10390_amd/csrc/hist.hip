@@ -32,30 +32,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStrea
 }
 
 // ----------------------------------------------------------------------------
-// Compressed 2^16-bin histogram of 16-bit keys, one per workgroup.
-//
-// Counter pair w holds bin 2w in its low half and bin 2w+1 in its high half.
-// Every increment is a returning LDS add, so the adding lane sees the old
-// word and can tell whether its add carried out of the low half (which also
-// bumped the high half by one) or out of the whole word.  Atomic adds are
-// linearised, so each wrap is seen by exactly one lane, which counts it in
-// wrap_lo[w] or wrap_word[w] (global, rare: one per 65536 keys of a bin).
-// Exact decode of the sums over all workgroups, with W_i the raw words:
-//   lo  = sum(W_i & 0xFFFF) + 2^16 * wrap_lo[w]
-//   V   = sum(W_i)          + 2^32 * wrap_word[w]     (= lo + 2^16 * hi)
-//   hi  = (V - lo) / 2^16
+// Compressed 2^16-bin histogram of 16-bit keys, one per workgroup
+// (hist16_add, fs_device.hpp).
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ void hist16_add(uint32_t* cnt, uint32_t key, uint32_t c,
-                                           uint32_t* wrap_lo, uint32_t* wrap_word) {
-    const uint32_t w = key >> 1;
-    const uint32_t inc = (key & 1u) ? (c << 16) : c;
-    const uint32_t old = atomicAdd(&cnt[w], inc);
-    const bool word_wrap = (old + inc) < old;
-    const bool lo_wrap = ((old & 0xFFFFu) + (inc & 0xFFFFu)) > 0xFFFFu;
-    if (__builtin_expect(word_wrap, 0)) atomicAdd(&wrap_word[w], 1u);
-    if (__builtin_expect(lo_wrap, 0)) atomicAdd(&wrap_lo[w], 1u);
-}
-
 __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
     const uint16_t* __restrict__ keys, uint64_t n, uint64_t head, uint64_t nvec,
     uint32_t* __restrict__ part, uint32_t* wrap_lo, uint32_t* wrap_word) {

@@ -196,6 +196,133 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
 }
 
 // ---------------------------------------------------------------------------
+// First histogram of a 16-bit pair sort: the compressed 2^16-bin histogram
+// of the whole key (Section III-B, Algorithm 1; counters packed two per LDS
+// word with exact wrap repair, hist16_add) and, in the same read, the tile
+// counts of digit 0 turned into block prefixes as in k_tile_hist.  The
+// 2^16-bin histogram gives both digit histograms for the plan (its
+// marginals) and, through its prefix, the sorted keys themselves
+// (Algorithm 5 with no trailing bits), so the last scatter pass only moves
+// the payloads.  One workgroup of kHist16Threads per CU (the counters take
+// 128 KiB of LDS).
+// ---------------------------------------------------------------------------
+template <int TILE>
+__global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uint32_t* __restrict__ part16,
+                                                                 uint32_t* wrap_lo, uint32_t* wrap_word) {
+    using K = uint16_t;
+    constexpr int THREADS = kHist16Threads;
+    constexpr int VK = 8;
+    constexpr int NW = THREADS / kWave;
+    constexpr int SETW = kRadix / 2;
+    constexpr int TPS = kHistVecs * THREADS * VK / TILE;  // tiles per step
+    static_assert(TPS >= 1 && TPS * TILE == kHistVecs * THREADS * VK, "whole tiles per step");
+    __shared__ uint32_t cnt[kHist16Words];
+    __shared__ uint32_t s_t[2][TPS][kHistCopies][SETW];
+
+    const K* src = static_cast<const K*>(a.in_k);
+    const int tid = threadIdx.x, wave = tid >> 6, copy = wave % kHistCopies;
+    for (int i = tid; i < kHist16Words; i += THREADS) cnt[i] = 0;
+    for (int i = tid; i < 2 * TPS * kHistCopies * SETW; i += THREADS) (&s_t[0][0][0][0])[i] = 0;
+
+    const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
+    const uint64_t blo = blocks * blockIdx.x / gridDim.x, bhi = blocks * (blockIdx.x + 1) / gridDim.x;
+    const uint64_t tlo = blo * a.block_tiles;
+    const uint64_t thi = bhi * a.block_tiles < a.tiles ? bhi * a.block_tiles : a.tiles;
+    const uint32_t head = (uint32_t)((reinterpret_cast<uintptr_t>(src) & 15) / sizeof(K));
+    uint32_t run_lo = 0, run_hi = 0;  // thread w < 128: bins 2w, 2w+1 of digit 0 inside the block
+    int par = 0;
+    (void)NW;
+    __syncthreads();
+    for (uint64_t t0 = tlo; t0 < thi; t0 += TPS, par ^= 1) {
+        const uint64_t lo = t0 * TILE;
+        const uint64_t hi_t = t0 + TPS < thi ? t0 + TPS : thi;
+        const uint64_t hi = hi_t * TILE < a.n ? hi_t * TILE : a.n;
+        const uint32_t cntk = (uint32_t)(hi - lo);
+        const uint32_t sh = (uint32_t)((lo + head) % VK);
+        const uint32_t nv = (sh + cntk + VK - 1) / VK;
+        const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - sh));
+        u32x4 q[kHistVecs + 1];
+#pragma unroll
+        for (int r = 0; r <= kHistVecs; ++r) {
+            const uint32_t v = tid + r * THREADS;
+            if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
+        }
+#pragma unroll
+        for (int r = 0; r <= kHistVecs; ++r) {
+            const uint32_t v = tid + r * THREADS;
+            if (r == kHistVecs && __builtin_amdgcn_readfirstlane(v) >= nv) break;  // wave-uniform
+            if (v < nv) {
+                K k[VK];
+                __builtin_memcpy(k, &q[r], 16);
+                const int32_t first = (int32_t)(v * VK) - (int32_t)sh;
+                const bool whole = first >= 0 && first + VK <= (int32_t)cntk &&
+                                   (uint32_t)first / TILE == (uint32_t)(first + VK - 1) / TILE;
+                bool same = whole;
+#pragma unroll
+                for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
+                const uint64_t active = ballot(true);
+                const uint32_t kw = __builtin_amdgcn_readfirstlane((uint32_t)k[0]);
+                const uint32_t set0 = whole ? (uint32_t)first / TILE : 0xFFFFFFFFu;
+                const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
+                if (ballot(same && (uint32_t)k[0] == kw && set0 == setw) == active) {
+                    // a whole wave holding one key value inside one tile: one add each
+                    if (lanes_below(active) == 0) {
+                        const uint32_t c = (uint32_t)VK * popc64(active);
+                        hist16_add(cnt, kw, c, wrap_lo, wrap_word);
+                        const uint32_t d = kw & 0xFFu;
+                        atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const int32_t idx = first + e;
+                        if (idx >= 0 && idx < (int32_t)cntk) {
+                            const uint32_t key = k[e];
+                            hist16_add(cnt, key, 1u, wrap_lo, wrap_word);
+                            const uint32_t d = key & 0xFFu;
+                            atomicAdd(&s_t[par][(uint32_t)idx / TILE][copy][d >> 1], 1u << ((d & 1) * 16));
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);  // count one vector at a time (register pressure)
+        }
+        __syncthreads();
+        if (tid < SETW) {
+            const uint32_t w = tid;
+            for (uint64_t t = t0; t < hi_t; ++t) {
+                const uint32_t set = (uint32_t)(t - t0);
+                uint32_t c = 0;
+#pragma unroll
+                for (int i = 0; i < kHistCopies; ++i) {
+                    c += s_t[par][set][i][w];
+                    s_t[par][set][i][w] = 0;
+                }
+                a.th[t * SETW + w] = run_lo | (run_hi << 16);
+                run_lo += c & 0xFFFFu;
+                run_hi += c >> 16;
+                if ((t + 1) % a.block_tiles == 0 || t + 1 == a.tiles) {
+                    uint32_t* bs = a.bsum + (t / a.block_tiles) * kRadix;
+                    bs[2 * w] = run_lo;
+                    bs[2 * w + 1] = run_hi;
+                    run_lo = run_hi = 0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t* dst = part16 + (uint64_t)blockIdx.x * kHist16Words;
+    for (int i = tid; i < kHist16Words; i += THREADS) dst[i] = cnt[i];
+}
+
+hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
+                              uint32_t* wrap_word, hipStream_t s) {
+    if (a.tile == 4096) k_tile_hist16<4096><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Pass plan from the first pass's workgroup totals: every digit's global
 // counts, their exclusive scans and the trivial digits (finish_plan).  One
 // block of kPlanThreads; each group of 256 threads sums a share of the
@@ -300,7 +427,7 @@ __global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
 // a request and its use is fixed and the wait at the top of the loop leaves
 // the previous tile's stores in flight.
 // ---------------------------------------------------------------------------
-template <typename K, typename V, int THREADS, int ITEMS, bool LATE>
+template <typename K, typename V, int THREADS, int ITEMS, bool LATE, bool SKIPK>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_tile_scatter(TiledArgs a, int pass) {
     constexpr int W = THREADS / kWave;
@@ -498,7 +625,9 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 const uint64_t dst = s_dst[digit_of<K>(kk, shift)] + qq;
                 const bool ok = in && dst < a.n;
                 bad_dst |= in && !(dst < a.n);
-                *(ok ? dst_k + dst : sink_k) = kk;
+                // SKIPK: the keys of this pass's output are written elsewhere
+                // (expanded from the 2^16-bin histogram)
+                if constexpr (!SKIPK) *(ok ? dst_k + dst : sink_k) = kk;
                 if constexpr (kHasVals) *(ok ? dst_v + dst : sink_v) = s_vals[qq];
                 // keep the compiler from hoisting every slot's loads at once
                 if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -544,7 +673,7 @@ int tiled_scatter_per_cu(int key_bytes, int val_bytes) {
     hipError_t e = hipErrorInvalidValue;
 #define FS_OCC(K, V, THR, IT, LATE)                                                                  \
     if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>())                                   \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE>, THR, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE, false>, THR, 0);
     FS_TILED_SHAPES(FS_OCC)
 #undef FS_OCC
     return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
@@ -558,6 +687,8 @@ static void launch_hist_t(const TiledArgs& a, int pass, uint32_t groups, hipStre
 
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
     if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, groups, s);
+    else if (key_bytes == 2 && a.tile == 8192) launch_hist_t<uint16_t, 8192>(a, pass, groups, s);
+    else if (key_bytes == 2 && a.tile == 16384) launch_hist_t<uint16_t, 16384>(a, pass, groups, s);
     else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, groups, s);
     else if (key_bytes == 4 && a.tile == 2048) launch_hist_t<uint32_t, 2048>(a, pass, groups, s);
     else if (key_bytes == 8 && a.tile == 4096) launch_hist_t<uint64_t, 4096>(a, pass, groups, s);
@@ -575,11 +706,14 @@ hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s) {
 }
 
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
-                               hipStream_t s) {
-#define FS_LAUNCH_SHAPE(K, V, THR, IT, LATE)                                  \
-    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>()) {          \
-        k_tile_scatter<K, V, THR, IT, LATE><<<groups, THR, 0, s>>>(a, pass);  \
-        return hipGetLastError();                                         \
+                               bool skip_keys, hipStream_t s) {
+#define FS_LAUNCH_SHAPE(K, V, THR, IT, LATE)                                              \
+    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>()) {                      \
+        if (skip_keys && sizeof(K) == 2 && val_size<V>() != 0)                            \
+            k_tile_scatter<K, V, THR, IT, LATE, true><<<groups, THR, 0, s>>>(a, pass);    \
+        else                                                                              \
+            k_tile_scatter<K, V, THR, IT, LATE, false><<<groups, THR, 0, s>>>(a, pass);   \
+        return hipGetLastError();                                                         \
     }
     FS_TILED_SHAPES(FS_LAUNCH_SHAPE)
 #undef FS_LAUNCH_SHAPE
