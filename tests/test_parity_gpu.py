@@ -131,6 +131,14 @@ def test_compressed_counters_wrap_exactly(gpu):
     assert np.array_equal(h, oracle.histogram(b, 0, 16))
     out = fs.sort_keys(dev(b))
     assert np.array_equal(host(out), np.sort(b))
+    # pair sorts build the same compressed histogram in their first read and
+    # expand their output keys from it
+    idx = np.arange(n, dtype=np.uint32)
+    for keys in (a, b):
+        ko, vo = fs.sort_pairs(dev(keys), dev(idx))
+        ek, ev = oracle.sort(keys, idx)
+        assert np.array_equal(host(ko), ek)
+        assert np.array_equal(host(vo), ev)
 
 
 def test_repeatable(gpu):
