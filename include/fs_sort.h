@@ -124,6 +124,70 @@ fs_status fs_sort_segmented(const fs_segment *d_segments, uint32_t num_segments,
                             uint64_t total_keys, uint64_t max_segment_keys, unsigned flags,
                             void *workspace, size_t *workspace_bytes, void *stream);
 
+/*
+ * Launch tuning of fs_sort_segmented.  Segments are binned by length and
+ * width on the device (the paper sizes its batches empirically,
+ * Section III-C); these fields choose, per bin, the digit width, the tile
+ * size and how many workgroups work on one segment:
+ *   small_max_keys[w]  w = 0, 1, 2 for 16-, 32-, 64-bit keys: segments of at
+ *                      most this many keys are sorted by ONE workgroup with
+ *                      8-bit digits entirely in LDS.  Clamped to what fits
+ *                      in LDS for the segment's key and payload width;
+ *                      values below 1024 are raised to 1024.
+ *   expand16_min_keys  16-bit keys-only segments of at least this many keys
+ *                      use ONE 16-bit digit instead: one workgroup builds the
+ *                      segment's compressed 2^16-bin histogram in LDS and
+ *                      writes the sorted keys from it (Sections III-A, III-E).
+ *                      This bin is checked first.  0xFFFFFFFF disables it.
+ *   expand16_split_keys  segments of that bin with at least this many keys
+ *                      are split over several workgroups (parts of 2^18
+ *                      keys whose histograms are merged in global memory);
+ *                      values below 2^18 are raised to 2^18, 0xFFFFFFFF
+ *                      never splits.
+ *   expand16_wgs_per_cu  workgroups per compute unit of that bin, 1..2.
+ *   tile_items         the remaining (large) segments are sorted with 8-bit
+ *                      digits by many workgroups, in tiles of
+ *                      256 * tile_items keys; tile_items is 8 or 16.
+ *   large_wgs_per_cu   workgroups per compute unit of the large-segment
+ *                      histogram and scatter launches, 1..8.
+ *   small_wgs_per_cu   workgroups per compute unit of the LDS bin, 1..4.
+ * Every setting gives bit-identical results; only the speed differs.
+ */
+typedef struct {
+    uint32_t small_max_keys[3];
+    uint32_t expand16_min_keys;
+    uint32_t expand16_split_keys;
+    uint32_t expand16_wgs_per_cu;
+    uint32_t tile_items;
+    uint32_t large_wgs_per_cu;
+    uint32_t small_wgs_per_cu;
+} fs_seg_tuning;
+
+/* Writes the built-in default tuning to *out.  NULL out: FS_ERR_INVALID_ARG. */
+fs_status fs_segmented_default_tuning(fs_seg_tuning *out);
+
+/*
+ * Sets the process-wide tuning that fs_sort_segmented uses (copied; NULL
+ * restores the defaults).  A field out of range gives FS_ERR_INVALID_ARG
+ * and leaves the table unchanged.  Thread-safe; a call in flight keeps the
+ * tuning it started with.
+ */
+fs_status fs_set_segmented_tuning(const fs_seg_tuning *tuning);
+
+/* Reads the process-wide tuning into *out. */
+fs_status fs_get_segmented_tuning(fs_seg_tuning *out);
+
+/*
+ * fs_sort_segmented with an explicit tuning (NULL = the process-wide one);
+ * this is what an autotuner times.  Same arguments, results, workspace size
+ * and errors as fs_sort_segmented; a field out of range gives
+ * FS_ERR_INVALID_ARG.
+ */
+fs_status fs_sort_segmented_tuned(const fs_segment *d_segments, uint32_t num_segments,
+                                  uint64_t total_keys, uint64_t max_segment_keys, unsigned flags,
+                                  const fs_seg_tuning *tuning, void *workspace,
+                                  size_t *workspace_bytes, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *fs_status_string(fs_status s);
 

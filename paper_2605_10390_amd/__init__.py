@@ -52,6 +52,12 @@ def lib():
     L.fs_digit_histograms.restype = i32
     L.fs_sort_segmented.argtypes = [vp, u32, u64, u64, ctypes.c_uint, vp, sz, vp]
     L.fs_sort_segmented.restype = i32
+    tp = ctypes.POINTER(SegTuning)
+    L.fs_sort_segmented_tuned.argtypes = [vp, u32, u64, u64, ctypes.c_uint, tp, vp, sz, vp]
+    L.fs_sort_segmented_tuned.restype = i32
+    for name in ("fs_segmented_default_tuning", "fs_set_segmented_tuning", "fs_get_segmented_tuning"):
+        getattr(L, name).argtypes = [tp]
+        getattr(L, name).restype = i32
     L.fs_profile_enable.argtypes = [i32]
     L.fs_profile_enable.restype = i32
     L.fs_profile_read.argtypes = [i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -199,6 +205,59 @@ SEGMENT_DTYPE = _np.dtype([("keys_in", _np.uint64), ("keys_out", _np.uint64),
                            ("n", _np.uint64), ("key_bits", _np.uint32), ("val_bytes", _np.uint32)])
 
 
+class SegTuning(ctypes.Structure):
+    """fs_seg_tuning: per-bin launch choices of fs_sort_segmented (digit
+    width via the 16-bit-digit bin, tile size, workgroups per CU)."""
+    _fields_ = [("small_max_keys", ctypes.c_uint32 * 3), ("expand16_min_keys", ctypes.c_uint32),
+                ("expand16_split_keys", ctypes.c_uint32), ("expand16_wgs_per_cu", ctypes.c_uint32),
+                ("tile_items", ctypes.c_uint32), ("large_wgs_per_cu", ctypes.c_uint32),
+                ("small_wgs_per_cu", ctypes.c_uint32)]
+
+    FIELDS = ("small_max_keys", "expand16_min_keys", "expand16_split_keys", "expand16_wgs_per_cu",
+              "tile_items", "large_wgs_per_cu", "small_wgs_per_cu")
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f in self.FIELDS}
+        d["small_max_keys"] = list(self.small_max_keys)
+        return d
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for f in cls.FIELDS:
+            if f == "small_max_keys":
+                t.small_max_keys[:] = [int(v) for v in d[f]]
+            else:
+                setattr(t, f, int(d[f]))
+        return t
+
+    def copy(self):
+        return SegTuning.from_dict(self.as_dict())
+
+
+def default_tuning():
+    t = SegTuning()
+    st = lib().fs_segmented_default_tuning(ctypes.byref(t))
+    if st != FS_OK:
+        raise FsError(st, "fs_segmented_default_tuning")
+    return t
+
+
+def get_tuning():
+    t = SegTuning()
+    st = lib().fs_get_segmented_tuning(ctypes.byref(t))
+    if st != FS_OK:
+        raise FsError(st, "fs_get_segmented_tuning")
+    return t
+
+
+def set_tuning(t):
+    """Set the process-wide tuning used by fs_sort_segmented (None = defaults)."""
+    st = lib().fs_set_segmented_tuning(ctypes.byref(t) if t is not None else None)
+    if st != FS_OK:
+        raise FsError(st, "fs_set_segmented_tuning")
+
+
 def sort_segmented_workspace_bytes(count, total_keys, max_segment_keys):
     size = ctypes.c_size_t(0)
     st = lib().fs_sort_segmented(None, int(count), int(total_keys), int(max_segment_keys), 0, None,
@@ -248,14 +307,21 @@ class SegmentBatch:
     def workspace_bytes(self):
         return sort_segmented_workspace_bytes(self.count, self.total_keys, self.max_segment_keys)
 
-    def run(self, workspace=None, stream=None):
+    def run(self, workspace=None, stream=None, tuning=None):
+        """One fs_sort_segmented call (fs_sort_segmented_tuned when `tuning`
+        is given); returns the workspace."""
         ws = workspace or Workspace(self.d_desc.device)
         buf = ws.get(self.workspace_bytes())
         size = ctypes.c_size_t(buf.numel())
         s = stream if stream is not None else torch.cuda.current_stream(self.d_desc.device)
-        st = lib().fs_sort_segmented(_ptr(self.d_desc), self.count, self.total_keys,
-                                     self.max_segment_keys, 0, _ptr(buf), ctypes.byref(size),
-                                     ctypes.c_void_p(s.cuda_stream))
+        if tuning is None:
+            st = lib().fs_sort_segmented(_ptr(self.d_desc), self.count, self.total_keys,
+                                         self.max_segment_keys, 0, _ptr(buf), ctypes.byref(size),
+                                         ctypes.c_void_p(s.cuda_stream))
+        else:
+            st = lib().fs_sort_segmented_tuned(_ptr(self.d_desc), self.count, self.total_keys,
+                                               self.max_segment_keys, 0, ctypes.byref(tuning), _ptr(buf),
+                                               ctypes.byref(size), ctypes.c_void_p(s.cuda_stream))
         if st != FS_OK:
             raise FsError(st, "fs_sort_segmented")
         return ws
@@ -288,7 +354,7 @@ class CapturedSort:
         self.graph.replay()
 
 
-def sort_segmented(segments, workspace=None):
+def sort_segmented(segments, workspace=None, tuning=None):
     """Sort every (keys_in, keys_out, vals_in, vals_out) segment independently
     in one call; returns the workspace (its error word is 0 on success)."""
-    return SegmentBatch(segments).run(workspace)
+    return SegmentBatch(segments).run(workspace, tuning=tuning)

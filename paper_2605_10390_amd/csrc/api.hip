@@ -6,6 +6,7 @@
 #include "fs_internal.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace fs {
 
@@ -276,16 +277,63 @@ fs_status fs_digit_histograms(const void* keys, uint64_t n, int key_bits, int di
     return FS_OK;
 }
 
+namespace {
+// built-in defaults (what the autotuner picked for a log-normal mix of
+// 16- and 32-bit segments on MI355X): the LDS bin takes whatever fits,
+// 16-bit keys-only segments from 16384 keys take the 16-bit-digit bin (split
+// from 2^18 keys), tiles of 4096 keys, three workgroups per CU in the large
+// bin and two in the LDS bin
+constexpr fs_seg_tuning kDefaultTuning = {{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, 16384u, 1u << 18, 1u, 16u, 3u, 2u};
+std::mutex g_tuning_mu;
+fs_seg_tuning g_tuning = kDefaultTuning;
+}  // namespace
+
+fs_status fs_segmented_default_tuning(fs_seg_tuning* out) {
+    if (!out) return FS_ERR_INVALID_ARG;
+    *out = kDefaultTuning;
+    return FS_OK;
+}
+
+fs_status fs_set_segmented_tuning(const fs_seg_tuning* tuning) {
+    const fs_seg_tuning t = tuning ? *tuning : kDefaultTuning;
+    if (!fs::seg_tuning_valid(t)) return FS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning = t;
+    return FS_OK;
+}
+
+fs_status fs_get_segmented_tuning(fs_seg_tuning* out) {
+    if (!out) return FS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    *out = g_tuning;
+    return FS_OK;
+}
+
 fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments, uint64_t total_keys,
                             uint64_t max_segment_keys, unsigned flags, void* workspace,
                             size_t* workspace_bytes, void* stream) {
+    return fs_sort_segmented_tuned(d_segments, num_segments, total_keys, max_segment_keys, flags, nullptr,
+                                   workspace, workspace_bytes, stream);
+}
+
+fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_segments, uint64_t total_keys,
+                                  uint64_t max_segment_keys, unsigned flags, const fs_seg_tuning* tuning,
+                                  void* workspace, size_t* workspace_bytes, void* stream) {
     using namespace fs;
     if (flags != FS_FLAG_NONE || !workspace_bytes) return FS_ERR_INVALID_ARG;
+    fs_seg_tuning tune;
+    if (tuning) {
+        tune = *tuning;
+    } else {
+        std::lock_guard<std::mutex> lk(g_tuning_mu);
+        tune = g_tuning;
+    }
+    if (!seg_tuning_valid(tune)) return FS_ERR_INVALID_ARG;
     if (max_segment_keys > kSegMaxKeys) return FS_ERR_UNSUPPORTED;
     if (total_keys > kMaxKeys) return FS_ERR_INVALID_ARG;
     const uint32_t nseg = num_segments;
     const uint32_t max_tiles = seg_max_tiles(total_keys, nseg);
-    const uint64_t nl_max = std::min<uint64_t>(nseg, total_keys / (kSegMinSmallCap + 1) + 1);
+    const uint64_t nl_max = std::min<uint64_t>(nseg, total_keys / (kSegMinSmallMax + 1) + 1);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -294,6 +342,10 @@ fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments,
     };
     const size_t o_err = take(4 * (1 + 128));
     const size_t o_small = take(4ull * nseg);
+    const size_t o_expand = take(4ull * nseg);
+    const uint64_t nx_max = std::min<uint64_t>(nseg, total_keys / kX16MinSplit);
+    const size_t o_x16p = take(4ull * (nx_max + 1));
+    const size_t o_x16h = take(4ull * 65536 * nx_max);
     const size_t o_large = take(4ull * 9 * nseg);
     const size_t o_tp = take(4ull * (nseg + 1));
     const size_t o_ep = take(8ull * (nseg + 1));
@@ -301,6 +353,7 @@ fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments,
     const size_t o_hist = take(4ull * nl_max * 8 * kRadix);
     const size_t o_plan = take(4ull * nl_max * 9);
     const size_t o_state = take(4ull * max_tiles * kRadix);
+    const size_t o_tdesc = take(sizeof(SegTileDesc) * (size_t)max_tiles);
     const size_t o_tk = take(8ull * total_keys);
     const size_t o_tv = take(8ull * total_keys);
     const size_t need = off;
@@ -322,6 +375,9 @@ fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments,
     x.err = reinterpret_cast<uint32_t*>(w + o_err);
     x.ctr = x.err + 1;
     x.small_list = reinterpret_cast<uint32_t*>(w + o_small);
+    x.expand_list = reinterpret_cast<uint32_t*>(w + o_expand);
+    x.x16_parts = reinterpret_cast<uint32_t*>(w + o_x16p);
+    x.x16_hist = reinterpret_cast<uint32_t*>(w + o_x16h);
     x.large_list = reinterpret_cast<uint32_t*>(w + o_large);
     x.tile_prefix = reinterpret_cast<uint32_t*>(w + o_tp);
     x.elem_prefix = reinterpret_cast<uint64_t*>(w + o_ep);
@@ -329,11 +385,12 @@ fs_status fs_sort_segmented(const fs_segment* d_segments, uint32_t num_segments,
     x.hist = reinterpret_cast<uint32_t*>(w + o_hist);
     x.plan = reinterpret_cast<uint32_t*>(w + o_plan);
     x.state = reinterpret_cast<uint32_t*>(w + o_state);
+    x.tdesc = reinterpret_cast<SegTileDesc*>(w + o_tdesc);
     x.tmp_k = w + o_tk;
     x.tmp_v = w + o_tv;
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.err, 1 + 128, 0, s));
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.state, (uint64_t)max_tiles * kRadix, 0, s));
-    FS_LAUNCH(FS_KERNEL_SEGMENTED, total_keys, launch_segmented(x, s));
+    FS_LAUNCH(FS_KERNEL_SEGMENTED, total_keys, launch_segmented(x, tune, s));
     return FS_OK;
 }
 

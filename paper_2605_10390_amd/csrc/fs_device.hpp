@@ -26,6 +26,17 @@ struct NoVal {};
 // 16-byte vector usable with the non-temporal load/store builtins
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// A pointer known to address global memory.  Pointers read from memory
+// (segment descriptors) are generic to the compiler, which then emits flat
+// instructions; flat accesses count against the LDS wait counter too, so
+// every LDS wait would also wait for them.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+    return (gptr<T>)p;
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // number of set bits of m in lanes below this lane

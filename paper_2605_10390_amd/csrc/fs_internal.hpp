@@ -111,7 +111,25 @@ hipError_t timed(int kind, uint64_t keys, hipStream_t s, F&& launch) {
 // ---- batched segmented sort (segmented.hip) --------------------------------
 constexpr uint32_t kSegSmallBytes = 32768;           // LDS bytes per buffer of a small segment
 constexpr uint64_t kSegMaxKeys = (1ull << 23) - 1;  // largest segment (look-back counts are 23-bit)
-constexpr uint32_t kSegMinSmallCap = (kSegSmallBytes - 16) / 16;
+constexpr uint32_t kSegMinSmallMax = 1024;         // least segment length a tuning may send to the large bin
+constexpr uint32_t kSegMinTile = 2048;             // smallest large-segment tile (sizes the tile arrays)
+constexpr uint32_t kX16Part = 1u << 18;            // keys per part of a long 16-bit-digit segment
+constexpr uint32_t kX16MinSplit = 1u << 18;        // least segment length a tuning may split
+
+// what a scatter pass needs of one tile of a large segment, in one 64-byte
+// record so that a workgroup finds it with a single load
+struct SegTileDesc {
+    const void* kin;
+    void* kout;
+    const void* vin;
+    void* vout;
+    uint64_t n;      // segment length
+    uint64_t eo;     // segment's offset in the temporary arrays
+    uint32_t q;      // segment's position in its class list
+    uint32_t t;      // tile index within the segment
+    uint32_t plan[2];  // 8 bits per pass: active, source (bits 1-2), destination (bits 3-4)
+};
+static_assert(sizeof(SegTileDesc) == 64, "tile record is one 64-byte line");
 
 struct SegCtx {
     const fs_segment* segs;
@@ -119,9 +137,16 @@ struct SegCtx {
     uint64_t max_seg;
     uint64_t total_keys;
     uint32_t max_tiles;
+    uint32_t tile;          // keys per large-segment tile
+    uint32_t small_max[3];  // per key width: longest segment of the LDS bin
+    uint32_t expand_min;    // 16-bit keys-only segments this long take the 16-bit-digit bin
+    uint32_t split_min;     //   and from this long get several workgroups
     uint32_t* err;
     uint32_t* ctr;          // queue counters, tile totals, tickets
     uint32_t* small_list;   // [nseg]
+    uint32_t* expand_list;  // [nseg]: long segments from the front, the rest from the back
+    uint32_t* x16_parts;    // [long segments + 1] part prefix
+    uint32_t* x16_hist;     // [long segments][65536] exact bin counts
     uint32_t* large_list;   // [9][nseg]
     uint32_t* tile_prefix;  // [nseg + 1] (current class)
     uint64_t* elem_prefix;  // [nseg + 1] (current class)
@@ -129,10 +154,13 @@ struct SegCtx {
     uint32_t* hist;         // [large segments][8][256]
     uint32_t* plan;         // [large segments][9]
     uint32_t* state;        // [max_tiles][256]
+    SegTileDesc* tdesc;     // [max_tiles]
     void* tmp_k;
     void* tmp_v;
 };
 uint32_t seg_max_tiles(uint64_t total_keys, uint32_t nseg);
-hipError_t launch_segmented(const SegCtx& x, hipStream_t s);
+// checks a tuning's ranges (false: invalid)
+bool seg_tuning_valid(const fs_seg_tuning& t);
+hipError_t launch_segmented(const SegCtx& x, const fs_seg_tuning& t, hipStream_t s);
 
 }  // namespace fs

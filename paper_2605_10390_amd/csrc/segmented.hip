@@ -5,11 +5,16 @@
 // batch is a caller segment and every segment gets exactly the result a
 // stand-alone sort would give it.  Segment descriptors live in device
 // memory, so the whole schedule is decided on the device:
-//   1. classify: each segment goes to the small queue (it fits in one
-//      workgroup's LDS) or to the large queue of its (key, value) width class;
-//   2. small segments: persistent workgroups pop the queue and sort each
-//      segment entirely in LDS (one read and one write of HBM);
-//   3. large segments, per width class: tile layout, per-segment digit
+//   1. classify: each segment goes to one of three bins by width and length
+//      (bounds from the launch tuning): the 16-bit-digit bin (16-bit keys
+//      without payload, long enough), the LDS bin (short enough to fit in
+//      one workgroup's LDS) or the large bin of its (key, value) class;
+//   2. 16-bit-digit bin: one workgroup per segment builds the compressed
+//      2^16-bin histogram in LDS and writes the sorted keys from it (one read
+//      and one write of HBM, no scatter);
+//   3. LDS bin: persistent workgroups pop the queue and sort each segment
+//      with 8-bit digits entirely in LDS (one read and one write of HBM);
+//   4. large segments, per width class: tile layout, per-segment digit
 //      histograms (one read), per-segment prefix scans and pass plans, then
 //      one single-sweep scatter launch per digit over the tiles of all large
 //      segments of the class at once, with decoupled look-back confined to
@@ -41,6 +46,10 @@ __host__ __device__ inline int ctr_large(int c) { return 2 + c; }
 __host__ __device__ inline int ctr_tiles(int c) { return 16 + c; }
 __host__ __device__ inline int ctr_ticket(int c, int j) { return 32 + 8 * c + j; }
 __host__ __device__ inline int ctr_seen() { return 119; }  // 64-bit running total of queued keys (8-byte aligned)
+__host__ __device__ inline int ctr_expand_long() { return 121; }  // 16-bit-digit bin: long segments queued
+__host__ __device__ inline int ctr_expand_rest() { return 122; }  //   other segments queued
+__host__ __device__ inline int ctr_expand_taken() { return 123; }
+__host__ __device__ inline int ctr_x16_parts() { return 124; }  // parts of the long segments
 
 // ---------------------------------------------------------------------------
 __global__ void k_seg_classify(SegCtx x) {
@@ -63,7 +72,15 @@ __global__ void k_seg_classify(SegCtx x) {
             continue;
         }
         const int kb = d.key_bits / 8, vb = d.val_bytes;
-        if (d.n <= small_cap(kb, vb)) {
+        const uint32_t small_max = x.small_max[kb == 2 ? 0 : kb == 4 ? 1 : 2];
+        if (kb == 2 && vb == 0 && d.n >= x.expand_min) {
+            // long segments (split over several workgroups) at the front
+            if (d.n >= x.split_min) {
+                x.expand_list[atomicAdd(&x.ctr[ctr_expand_long()], 1u)] = s;
+            } else {
+                x.expand_list[x.nseg - 1 - atomicAdd(&x.ctr[ctr_expand_rest()], 1u)] = s;
+            }
+        } else if (d.n <= small_cap(kb, vb) && d.n <= small_max) {
             const uint32_t i = atomicAdd(&x.ctr[0], 1u);
             x.small_list[i] = s;
         } else {
@@ -89,11 +106,68 @@ struct SmallShared {
     uint32_t run[kRadix];
     uint64_t wsum[4];
     uint32_t flag;
-    uint32_t seg;
+    uint32_t seg, next;
 };
 
+// Copy n elements from global memory into LDS, and back, with aligned
+// 16-byte accesses: elements outside [0, n) of a global block are masked on
+// loads (an aligned 16-byte block never leaves a mapped page) and partial
+// blocks at either end are stored element by element.
+template <typename T, int NT>
+__device__ __forceinline__ void global_to_lds(const T* src, T* lds, uint32_t n) {
+    constexpr int VK = 16 / (int)sizeof(T);
+    constexpr int U = 4;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(src);
+    const uintptr_t a0 = p & ~(uintptr_t)15;
+    const uint32_t lead = (uint32_t)((p - a0) / sizeof(T));
+    const uint32_t nv = (lead + n + VK - 1) / VK;
+    const gptr<const u32x4> vp = (gptr<const u32x4>)(a0);
+    for (uint32_t i0 = 0; i0 < nv; i0 += U * NT) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * NT + threadIdx.x;
+            v[u] = __builtin_nontemporal_load(&vp[i < nv ? i : nv - 1]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * NT + threadIdx.x;
+            const T* ev = reinterpret_cast<const T*>(&v[u]);
+#pragma unroll
+            for (int e = 0; e < VK; ++e) {
+                const int64_t idx = (int64_t)i * VK + e - lead;
+                if (i < nv && idx >= 0 && idx < (int64_t)n) lds[idx] = ev[e];
+            }
+        }
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void lds_to_global(const T* lds, T* dst, uint32_t n) {
+    constexpr int VK = 16 / (int)sizeof(T);
+    const uintptr_t p = reinterpret_cast<uintptr_t>(dst);
+    const uintptr_t a0 = p & ~(uintptr_t)15;
+    const int64_t lead = (int64_t)((p - a0) / sizeof(T));
+    const uint32_t nv = (uint32_t)((lead + n + VK - 1) / VK);
+    for (uint32_t i = threadIdx.x; i < nv; i += NT) {
+        const int64_t p0 = (int64_t)i * VK - lead;
+        if (p0 >= 0 && p0 + VK <= (int64_t)n) {
+            union {
+                T e[VK];
+                u32x4 v;
+            } b;
+#pragma unroll
+            for (int e = 0; e < VK; ++e) b.e[e] = lds[p0 + e];
+            __builtin_nontemporal_store(b.v, (gptr<u32x4>)(a0 + 16ull * i));
+        } else {
+            for (int e = 0; e < VK; ++e)
+                if (p0 + e >= 0 && p0 + e < (int64_t)n) to_global(dst)[p0 + e] = lds[p0 + e];
+        }
+    }
+}
+
 template <typename K, typename V>
-__device__ void sort_small(const fs_segment& d, SmallShared& sm) {
+__device__ __forceinline__ void sort_small(const fs_segment& d, SmallShared& sm) {
     constexpr bool kHasVals = !__is_same(V, NoVal);
     using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
     constexpr int D = sizeof(K);
@@ -101,21 +175,20 @@ __device__ void sort_small(const fs_segment& d, SmallShared& sm) {
     const uint32_t n = (uint32_t)d.n;
     const uint32_t cap = small_cap(kb, vb);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    K* kbuf[2] = {reinterpret_cast<K*>(sm.buf[0]), reinterpret_cast<K*>(sm.buf[1])};
-    VS* vbuf[2] = {reinterpret_cast<VS*>(sm.buf[0] + small_val_offset(cap, kb)),
-                   reinterpret_cast<VS*>(sm.buf[1] + small_val_offset(cap, kb))};
-    const K* kin = static_cast<const K*>(d.keys_in);
-    for (uint32_t i = tid; i < n; i += kSmallThreads) {
-        kbuf[0][i] = kin[i];
-        if constexpr (kHasVals) vbuf[0][i] = static_cast<const VS*>(d.vals_in)[i];
-    }
+    // buffers are addressed by index into the shared array (not through a
+    // table of pointers) so that every access compiles to an LDS instruction
+    const uint32_t voff = small_val_offset(cap, kb);
+    auto kbuf = [&](int c) { return reinterpret_cast<K*>(sm.buf[c]); };
+    auto vbuf = [&](int c) { return reinterpret_cast<VS*>(sm.buf[c] + voff); };
+    global_to_lds<K, kSmallThreads>(static_cast<const K*>(d.keys_in), kbuf(0), n);
+    if constexpr (kHasVals) global_to_lds<VS, kSmallThreads>(static_cast<const VS*>(d.vals_in), vbuf(0), n);
     __syncthreads();
     int cur = 0;
     for (int j = 0; j < D; ++j) {
         const int shift = 8 * j;
         if (tid < kRadix) sm.hist[tid] = 0;
         __syncthreads();
-        for (uint32_t i = tid; i < n; i += kSmallThreads) atomicAdd(&sm.hist[digit_of<K>(kbuf[cur][i], shift)], 1u);
+        for (uint32_t i = tid; i < n; i += kSmallThreads) atomicAdd(&sm.hist[digit_of<K>(kbuf(cur)[i], shift)], 1u);
         __syncthreads();
         const uint32_t h = tid < kRadix ? sm.hist[tid] : 0;
         const int trivial = __syncthreads_or(h == n);
@@ -136,7 +209,7 @@ __device__ void sort_small(const fs_segment& d, SmallShared& sm) {
             for (int k = 0; k < kSmallItems; ++k) {
                 const uint32_t idx = wbase + k * kWave + lane;
                 const bool valid = idx < cnt;
-                key[k] = valid ? kbuf[cur][base + idx] : (K)0;
+                key[k] = valid ? kbuf(cur)[base + idx] : (K)0;
                 rank[k] = wave_rank(digit_of<K>(key[k], shift), valid, sm.peers[wave], sm.wcnt[wave]);
             }
             __syncthreads();
@@ -156,8 +229,8 @@ __device__ void sort_small(const fs_segment& d, SmallShared& sm) {
                 if (idx < cnt) {
                     const uint32_t pos = sm.wcnt[wave][digit_of<K>(key[k], shift)] + rank[k];
                     if (pos < n) {
-                        kbuf[1 - cur][pos] = key[k];
-                        if constexpr (kHasVals) vbuf[1 - cur][pos] = vbuf[cur][base + idx];
+                        kbuf(1 - cur)[pos] = key[k];
+                        if constexpr (kHasVals) vbuf(1 - cur)[pos] = vbuf(cur)[base + idx];
                     }
                 }
             }
@@ -165,11 +238,8 @@ __device__ void sort_small(const fs_segment& d, SmallShared& sm) {
         }
         cur = 1 - cur;
     }
-    K* kout = static_cast<K*>(d.keys_out);
-    for (uint32_t i = tid; i < n; i += kSmallThreads) {
-        kout[i] = kbuf[cur][i];
-        if constexpr (kHasVals) static_cast<VS*>(d.vals_out)[i] = vbuf[cur][i];
-    }
+    lds_to_global<K, kSmallThreads>(kbuf(cur), static_cast<K*>(d.keys_out), n);
+    if constexpr (kHasVals) lds_to_global<VS, kSmallThreads>(vbuf(cur), static_cast<VS*>(d.vals_out), n);
     __syncthreads();
 }
 
@@ -178,9 +248,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_seg_small(SegCtx x) {
     const int tid = threadIdx.x;
     for (int i = tid; i < kSmallWaves * kRadix; i += kSmallThreads) (&sm.peers[0][0])[i] = 0;
     const uint32_t nsmall = x.ctr[0];
+    // queue entries are popped one segment ahead so that the pop overlaps the work
+    if (tid == 0) sm.next = add_agent(&x.ctr[1], 1u);
     for (;;) {
         __syncthreads();
-        if (tid == 0) sm.seg = add_agent(&x.ctr[1], 1u);
+        if (tid == 0) {
+            sm.seg = sm.next;
+            if (sm.seg < nsmall) sm.next = add_agent(&x.ctr[1], 1u);
+        }
         __syncthreads();
         const uint32_t i = sm.seg;
         if (i >= nsmall) break;
@@ -200,11 +275,382 @@ __global__ __launch_bounds__(kSmallThreads) void k_seg_small(SegCtx x) {
 }
 
 // ---------------------------------------------------------------------------
+// 16-bit-digit bin: 16-bit keys without payload.
+//
+// The whole key is one digit, so the histogram is the multiset of the
+// segment and the sorted output is written straight from its prefix sums
+// (Section III-E, with no index array).  The 2^16 counters are packed two per
+// 32-bit LDS word (Section III-D.1), which is what lets the full histogram
+// sit in one workgroup's LDS.  A count past 65535 needs the carry repair of
+// the packed pair; carries are rare (one per 65536 keys of a bin) and are
+// logged in LDS, with a bit per word that has any.
+//
+// Medium segments take one workgroup each.  Long segments are split into
+// parts of kX16Part keys: one launch builds each part's histogram in LDS and
+// adds its exact counts to the segment's global histogram (the local-then-
+// global merge of Section III-A); a second launch gives each part of the
+// OUTPUT a workgroup that loads the segment's counts back into the packed LDS
+// form, takes their prefix sums and writes its share of the sorted keys.
+// ---------------------------------------------------------------------------
+constexpr int kExpThreads = 1024;
+constexpr int kExpGroups = 4096;    // 16-bin groups of the 2^16 bins
+constexpr int kExpEvents = 512;     // carry log (a segment below 2^23 keys logs fewer than 256)
+
+struct ExpandShared {
+    __attribute__((aligned(16))) uint32_t cnt[kHist16Words];  // bins 2w (low half) and 2w+1 (high half)
+    uint32_t gpre[kExpGroups];            // exclusive prefix of every 16-bin group
+    uint32_t carried[kHist16Words / 32];  // one bit per word that logged a carry
+    uint32_t ev[kExpEvents];              // word | (1 << 31 for a carry out of the whole word)
+    uint32_t wsum[kExpThreads / kWave];
+    uint32_t nev;
+    uint32_t item, next;                  // queue entries: current and prefetched
+};
+
+// exact count of bin v
+__device__ __forceinline__ uint32_t exp_count(const ExpandShared& sm, uint32_t v, uint32_t nev) {
+    const uint32_t w = v >> 1;
+    const uint32_t word = sm.cnt[w];
+    if (__builtin_expect(!((sm.carried[w >> 5] >> (w & 31)) & 1u), 1))
+        return (v & 1u) ? (word >> 16) : (word & 0xFFFFu);
+    uint32_t nlo = 0, nword = 0;
+    for (uint32_t e = 0; e < nev; ++e) {
+        const uint32_t r = sm.ev[e];
+        if ((r & 0x7FFFFFFFu) == w) {
+            if (r >> 31) ++nword;
+            else ++nlo;
+        }
+    }
+    // sum of the increments S = lo + 2^16 * hi; the word holds S mod 2^32
+    const uint64_t lo = (uint64_t)(word & 0xFFFFu) + ((uint64_t)nlo << 16);
+    const uint64_t sum = (uint64_t)word + ((uint64_t)nword << 32);
+    return (v & 1u) ? (uint32_t)((sum - lo) >> 16) : (uint32_t)lo;
+}
+
+__device__ __forceinline__ void exp_log(ExpandShared& sm, uint32_t w, uint32_t nlo, uint32_t nword) {
+    atomicOr(&sm.carried[w >> 5], 1u << (w & 31));
+    const uint32_t e = atomicAdd(&sm.nev, nlo + nword);
+    for (uint32_t k = 0; k < nword; ++k)
+        if (e + k < (uint32_t)kExpEvents) sm.ev[e + k] = w | 0x80000000u;
+    for (uint32_t k = 0; k < nlo; ++k)
+        if (e + nword + k < (uint32_t)kExpEvents) sm.ev[e + nword + k] = w;
+}
+
+__device__ __forceinline__ void exp_add_logged(ExpandShared& sm, uint32_t key) {
+    const uint32_t w = key >> 1;
+    const uint32_t inc = (key & 1u) ? 0x10000u : 1u;
+    const uint32_t old = atomicAdd(&sm.cnt[w], inc);
+    const bool word_wrap = old + inc < old;
+    const bool lo_wrap = (old & 0xFFFFu) + (inc & 0xFFFFu) > 0xFFFFu;
+    if (__builtin_expect(word_wrap || lo_wrap, 0)) exp_log(sm, w, (uint32_t)lo_wrap, (uint32_t)word_wrap);
+}
+
+__device__ __forceinline__ void exp_clear(ExpandShared& sm) {
+    const int tid = threadIdx.x;
+    u32x4* c4 = reinterpret_cast<u32x4*>(sm.cnt);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (int i = tid; i < kHist16Words / 4; i += kExpThreads) c4[i] = z;
+    for (int i = tid; i < kHist16Words / 32; i += kExpThreads) sm.carried[i] = 0;
+    if (tid == 0) sm.nev = 0;
+}
+
+// histogram of keys [0, n) of `keys`: aligned 16-byte loads, keys outside
+// the range masked (an aligned 16-byte block never leaves a mapped page)
+__device__ __forceinline__ void exp_hist(ExpandShared& sm, const uint16_t* keys, uint64_t n) {
+    const int tid = threadIdx.x;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(keys);
+    const uintptr_t a0 = p & ~(uintptr_t)15;
+    const uint64_t lead = (p - a0) >> 1;
+    const uint64_t nv = (lead + n + 7) >> 3;
+    const gptr<const u32x4> vp = (gptr<const u32x4>)(a0);
+    const bool may_carry = n > 0xFFFFu;  // no bin of a shorter range passes 65535
+    constexpr int U = 4;                 // vectors in flight per thread
+    for (uint64_t i0 = 0; i0 < nv; i0 += U * kExpThreads) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kExpThreads + tid;
+            v[u] = __builtin_nontemporal_load(&vp[i < nv ? i : nv - 1]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kExpThreads + tid;
+            const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint64_t idx = i * 8 + e;  // element index from a0; valid in [lead, lead + n)
+                if (idx < lead || idx >= lead + n) continue;
+                const uint32_t key = (wv[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                if (may_carry) exp_add_logged(sm, key);
+                else atomicAdd(&sm.cnt[key >> 1], (key & 1u) ? 0x10000u : 1u);
+            }
+        }
+    }
+}
+
+// exclusive prefix of the 16-bin groups (thread t owns groups 4t..4t+3)
+__device__ __forceinline__ void exp_scan(ExpandShared& sm, uint32_t nev) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t gs[4], tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int g = 4 * tid + k;
+        uint32_t sum = 0;
+        const u32x4* c4 = reinterpret_cast<const u32x4*>(&sm.cnt[8 * g]);
+        const uint32_t flags = (sm.carried[(8 * g) >> 5] >> ((8 * g) & 31)) & 0xFFu;
+        if (flags == 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const u32x4 q = c4[h];
+                sum += (q.x & 0xFFFFu) + (q.x >> 16) + (q.y & 0xFFFFu) + (q.y >> 16) + (q.z & 0xFFFFu) +
+                       (q.z >> 16) + (q.w & 0xFFFFu) + (q.w >> 16);
+            }
+        } else {
+            for (int b = 0; b < 16; ++b) sum += exp_count(sm, 16u * g + b, nev);
+        }
+        gs[k] = sum;
+        tot += sum;
+    }
+    uint32_t inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) sm.wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += sm.wsum[w];
+    uint32_t r = before + inc - tot;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sm.gpre[4 * tid + k] = r;
+        r += gs[k];
+    }
+}
+
+// bin holding output position pos: the last group at or after g0 whose
+// prefix is <= pos, then its bins; start/end of the bin are returned
+__device__ __forceinline__ uint32_t exp_locate(const ExpandShared& sm, uint32_t pos, uint32_t g0,
+                                               uint32_t nev, uint32_t& end) {
+    uint32_t g = g0, len = (uint32_t)kExpGroups - g0;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        if (sm.gpre[g + half] <= pos) g += half;
+        len -= half;
+    }
+    uint32_t v = 16u * g, start = sm.gpre[g], c = exp_count(sm, v, nev);
+    while (start + c <= pos && v < 0xFFFFu) {  // within the group (bounded even if counts were wrong)
+        start += c;
+        ++v;
+        c = exp_count(sm, v, nev);
+    }
+    end = start + c;
+    return v;
+}
+
+// write sorted positions [pa, pb) of the n-key output `out` from the LDS
+// histogram.  The output is cut into aligned 16-byte blocks (8 keys); block i
+// goes to this workgroup when its first in-range position lies in [pa, pb),
+// and lane i of the block loop writes block i, so a wave stores 1 KB of
+// contiguous output per instruction.
+__device__ __forceinline__ void exp_out(const ExpandShared& sm, uint16_t* out, uint64_t n, uint64_t pa,
+                                        uint64_t pb, uint32_t nev) {
+    const int tid = threadIdx.x;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(out);
+    const uintptr_t a0 = p & ~(uintptr_t)15;
+    const uint64_t lead = (p - a0) >> 1;
+    // blocks whose first in-range position is in [pa, pb)
+    const uint64_t i_lo = pa == 0 ? 0 : (pa + lead + 7) >> 3;
+    const uint64_t i_hi = pb >= n ? (lead + n + 7) >> 3 : (pb + lead + 7) >> 3;
+    for (uint64_t i = i_lo + tid; i < i_hi; i += kExpThreads) {
+        const int64_t p0 = (int64_t)(i * 8) - (int64_t)lead;  // position of the block's first element
+        const uint32_t first = (uint32_t)(p0 < 0 ? 0 : p0);
+        uint32_t end;
+        uint32_t v = exp_locate(sm, first, 0, nev, end);
+        uint32_t o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t pos = p0 + e;
+            if (pos >= (int64_t)first && (uint64_t)pos < n && (uint32_t)pos >= end) {
+                // next bins: a short walk, else a search from the current group
+                int steps = 0;
+                while ((uint32_t)pos >= end && steps < 4 && v < 0xFFFFu) {
+                    ++v;
+                    end += exp_count(sm, v, nev);
+                    ++steps;
+                }
+                if ((uint32_t)pos >= end) v = exp_locate(sm, (uint32_t)pos, v >> 4, nev, end);
+            }
+            o[e] = v;
+        }
+        if (p0 >= 0 && (uint64_t)(p0 + 8) <= n) {
+            u32x4 q;
+            q.x = o[0] | (o[1] << 16);
+            q.y = o[2] | (o[3] << 16);
+            q.z = o[4] | (o[5] << 16);
+            q.w = o[6] | (o[7] << 16);
+            __builtin_nontemporal_store(q, (gptr<u32x4>)(a0 + 16 * i));
+        } else {
+            for (int e = 0; e < 8; ++e) {
+                const int64_t pos = p0 + e;
+                if (pos >= 0 && (uint64_t)pos < n) to_global(out)[pos] = (uint16_t)o[e];
+            }
+        }
+    }
+}
+
+// medium segments: one workgroup per segment, queue entries popped one
+// segment ahead so that the pop and the descriptor load overlap the work
+__global__ __launch_bounds__(kExpThreads) void k_seg_expand16(SegCtx x) {
+    __shared__ ExpandShared sm;
+    const int tid = threadIdx.x;
+    const uint32_t nmed = x.ctr[ctr_expand_rest()];
+    uint32_t* taken = &x.ctr[ctr_expand_taken()];
+    if (tid == 0) sm.next = add_agent(taken, 1u);
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            sm.item = sm.next;
+            if (sm.item < nmed) sm.next = add_agent(taken, 1u);
+        }
+        __syncthreads();
+        const uint32_t i = sm.item;
+        if (i >= nmed) break;
+        const fs_segment d = x.segs[x.expand_list[x.nseg - 1 - i]];
+        exp_clear(sm);
+        __syncthreads();
+        exp_hist(sm, static_cast<const uint16_t*>(d.keys_in), d.n);
+        __syncthreads();
+        const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
+        if (tid == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(x.err, 64u);
+        exp_scan(sm, nev);
+        __syncthreads();
+        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, 0, d.n, nev);
+    }
+}
+
+// ---- long segments (several workgroups each) --------------------------------
+
+// part prefix over the long segments and the total part count (one block)
+__global__ __launch_bounds__(1024) void k_seg_x16_layout(SegCtx x) {
+    __shared__ uint32_t ws[16];
+    const uint32_t cnt = x.ctr[ctr_expand_long()];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t per = (cnt + 1023) / 1024;
+    const uint32_t q0 = tid * per, q1 = q0 + per < cnt ? q0 + per : cnt;
+    uint32_t lp = 0;
+    for (uint32_t q = q0; q < q1; ++q) lp += (uint32_t)((x.segs[x.expand_list[q]].n + kX16Part - 1) / kX16Part);
+    uint32_t ip = lp;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t a = __shfl_up(ip, off, 64);
+        if (lane >= off) ip += a;
+    }
+    if (lane == 63) ws[wave] = ip;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) before += ws[w];
+        total += ws[w];
+    }
+    uint32_t r = before + ip - lp;
+    for (uint32_t q = q0; q < q1; ++q) {
+        x.x16_parts[q] = r;
+        r += (uint32_t)((x.segs[x.expand_list[q]].n + kX16Part - 1) / kX16Part);
+    }
+    if (tid == 0) {
+        x.x16_parts[cnt] = total;
+        x.ctr[ctr_x16_parts()] = total;
+    }
+}
+
+__global__ void k_seg_x16_zero(SegCtx x) {
+    const uint64_t words = (uint64_t)x.ctr[ctr_expand_long()] * 65536;
+    u32x4* g4 = reinterpret_cast<u32x4*>(x.x16_hist);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words / 4;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        g4[i] = z;
+}
+
+// the long segment holding part `part` (last q with x16_parts[q] <= part)
+__device__ __forceinline__ uint32_t x16_segment_of(const SegCtx& x, uint32_t part, uint32_t nlong) {
+    uint32_t q = 0, len = nlong;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        if (x.x16_parts[q + half] <= part) q += half;
+        len -= half;
+    }
+    return q;
+}
+
+__global__ __launch_bounds__(kExpThreads) void k_seg_x16_hist(SegCtx x) {
+    __shared__ ExpandShared sm;
+    const int tid = threadIdx.x;
+    const uint32_t nlong = x.ctr[ctr_expand_long()];
+    const uint32_t parts = x.ctr[ctr_x16_parts()];
+    for (uint32_t part = blockIdx.x; part < parts; part += gridDim.x) {
+        const uint32_t q = x16_segment_of(x, part, nlong);
+        const fs_segment d = x.segs[x.expand_list[q]];
+        const uint64_t b0 = (uint64_t)(part - x.x16_parts[q]) * kX16Part;
+        const uint64_t m = d.n - b0 < kX16Part ? d.n - b0 : kX16Part;
+        exp_clear(sm);
+        __syncthreads();
+        exp_hist(sm, static_cast<const uint16_t*>(d.keys_in) + b0, m);
+        __syncthreads();
+        const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
+        if (tid == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(x.err, 64u);
+        // add the exact nonzero counts to the segment's histogram
+        uint32_t* gh = x.x16_hist + (uint64_t)q * 65536;
+        for (uint32_t w = tid; w < (uint32_t)kHist16Words; w += kExpThreads) {
+            const uint32_t word = sm.cnt[w];
+            const bool carried = (sm.carried[w >> 5] >> (w & 31)) & 1u;
+            const uint32_t lo = carried ? exp_count(sm, 2 * w, nev) : word & 0xFFFFu;
+            const uint32_t hi = carried ? exp_count(sm, 2 * w + 1, nev) : word >> 16;
+            if (lo) atomicAdd(&gh[2 * w], lo);
+            if (hi) atomicAdd(&gh[2 * w + 1], hi);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kExpThreads) void k_seg_x16_out(SegCtx x) {
+    __shared__ ExpandShared sm;
+    const int tid = threadIdx.x;
+    const uint32_t nlong = x.ctr[ctr_expand_long()];
+    const uint32_t parts = x.ctr[ctr_x16_parts()];
+    for (uint32_t part = blockIdx.x; part < parts; part += gridDim.x) {
+        const uint32_t q = x16_segment_of(x, part, nlong);
+        const fs_segment d = x.segs[x.expand_list[q]];
+        const uint64_t pa = (uint64_t)(part - x.x16_parts[q]) * kX16Part;
+        const uint64_t pb = d.n - pa < kX16Part ? d.n : pa + kX16Part;
+        // the segment's exact counts back into the packed LDS form; a pair
+        // whose low count or whole sum overflows is represented by carry
+        // events that decode to the exact counts
+        if (tid < kHist16Words / 32) sm.carried[tid] = 0;
+        if (tid == 0) sm.nev = 0;
+        __syncthreads();
+        const uint32_t* gh = x.x16_hist + (uint64_t)q * 65536;
+        for (uint32_t w = tid; w < (uint32_t)kHist16Words; w += kExpThreads) {
+            const uint32_t lo = gh[2 * w], hi = gh[2 * w + 1];
+            const uint64_t sum = (uint64_t)lo + ((uint64_t)hi << 16);
+            sm.cnt[w] = (uint32_t)sum;
+            if (__builtin_expect(lo > 0xFFFFu || (sum >> 32) != 0, 0))
+                exp_log(sm, w, lo >> 16, (uint32_t)(sum >> 32));
+        }
+        __syncthreads();
+        const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
+        if (tid == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(x.err, 64u);
+        exp_scan(sm, nev);
+        __syncthreads();
+        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, pa, pb, nev);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Large segments of one width class.
 // ---------------------------------------------------------------------------
 constexpr int kSegTileThreads = 256;
-constexpr int kSegTileItems = 16;
-constexpr uint32_t kSegTile = kSegTileThreads * kSegTileItems;
 
 // tile and element prefixes over the class's large segments (one block)
 __global__ __launch_bounds__(1024) void k_seg_layout(SegCtx x, int c) {
@@ -217,7 +663,7 @@ __global__ __launch_bounds__(1024) void k_seg_layout(SegCtx x, int c) {
     uint64_t lt = 0, le = 0;
     for (uint32_t q = q0; q < q1; ++q) {
         const uint64_t n = x.segs[list[q]].n;
-        lt += (n + kSegTile - 1) / kSegTile;
+        lt += (n + x.tile - 1) / x.tile;
         le += n;
     }
     uint64_t it = lt, ie = le;
@@ -239,7 +685,7 @@ __global__ __launch_bounds__(1024) void k_seg_layout(SegCtx x, int c) {
         const uint64_t n = x.segs[list[q]].n;
         tp[q] = (uint32_t)rt;
         ep[q] = re;
-        rt += (n + kSegTile - 1) / kSegTile;
+        rt += (n + x.tile - 1) / x.tile;
         re += n;
     }
     if (tid == 0) {
@@ -256,50 +702,79 @@ __global__ void k_seg_tilemap(SegCtx x, int c) {
     }
 }
 
-// per-segment digit histograms: each workgroup walks a contiguous stretch of
-// tiles and flushes its LDS counts whenever the segment changes
+// per-segment digit histograms: each workgroup takes a contiguous stretch
+// of tiles and walks it one segment at a time, so the keys of a segment's
+// tiles are read in one pipelined loop and the LDS counts are flushed once
+// per segment.  Keys are read as aligned 16-byte vectors with the elements
+// outside the range masked (an aligned 16-byte block never leaves a mapped
+// page); when every valid lane of a wave has the same digit (long runs of one
+// value, skewed keys) one lane adds the whole count.
 template <typename K>
 __global__ __launch_bounds__(kSegTileThreads) void k_seg_hist(SegCtx x, int c) {
     constexpr int D = sizeof(K);
+    constexpr int VK = 16 / (int)sizeof(K);  // keys per vector
+    constexpr int U = 4;                     // vectors in flight per thread
     __shared__ uint32_t cnt[D][kRadix];
-    __shared__ uint32_t s_q;
     const uint32_t tiles = x.ctr[ctr_tiles(c)];
     const uint32_t* list = x.large_list + (uint64_t)c * x.nseg;
     const int tid = threadIdx.x;
     const uint32_t per = (tiles + gridDim.x - 1) / gridDim.x;
     const uint32_t g0 = blockIdx.x * per, g1 = g0 + per < tiles ? g0 + per : tiles;
     for (int i = tid; i < D * kRadix; i += kSegTileThreads) (&cnt[0][0])[i] = 0;
-    uint32_t qcur = 0xFFFFFFFFu;
-    auto flush = [&](uint32_t q) {
+    for (uint32_t g = g0; g < g1;) {
+        const uint32_t q = x.tile_seg[g];
+        const uint32_t tq0 = x.tile_prefix[q], tq1 = x.tile_prefix[q + 1];
+        const uint32_t ge = tq1 < g1 ? tq1 : g1;  // this workgroup's tiles of segment q: [g, ge)
+        const fs_segment d = x.segs[list[q]];
+        const uint64_t b0 = (uint64_t)(g - tq0) * x.tile;
+        const uint64_t b1 = (uint64_t)(ge - tq0) * x.tile < d.n ? (uint64_t)(ge - tq0) * x.tile : d.n;
+        const uint64_t count = b1 - b0;
+        const uintptr_t p = reinterpret_cast<uintptr_t>(static_cast<const K*>(d.keys_in) + b0);
+        const uintptr_t a0 = p & ~(uintptr_t)15;
+        const uint64_t lead = (p - a0) / sizeof(K);
+        const uint64_t nv = (lead + count + VK - 1) / VK;
+        const gptr<const u32x4> vp = (gptr<const u32x4>)(a0);
+        for (uint64_t i0 = 0; i0 < nv; i0 += U * kSegTileThreads) {
+            u32x4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * kSegTileThreads + tid;
+                v[u] = __builtin_nontemporal_load(&vp[i < nv ? i : nv - 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * kSegTileThreads + tid;
+                const K* kv = reinterpret_cast<const K*>(&v[u]);
+#pragma unroll
+                for (int e = 0; e < VK; ++e) {
+                    const uint64_t idx = i * VK + e;
+                    const bool valid = idx >= lead && idx < lead + count;
+                    const K key = kv[e];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        const uint32_t dg = digit_of<K>(key, 8 * j);
+                        const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                        const uint64_t act = ballot(valid);
+                        const uint64_t same = ballot(valid && dg == d0);
+                        if (act != 0 && same == act) {
+                            if (lanes_below(act) == 0 && valid) atomicAdd(&cnt[j][dg], popc64(act));
+                        } else if (valid) {
+                            atomicAdd(&cnt[j][dg], 1u);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
         uint32_t* h = x.hist + (uint64_t)q * 8 * kRadix;
         for (int i = tid; i < D * kRadix; i += kSegTileThreads) {
             const uint32_t v = (&cnt[0][0])[i];
             if (v) atomicAdd(&h[i], v);
             (&cnt[0][0])[i] = 0;
         }
-    };
-    for (uint32_t g = g0; g < g1; ++g) {
         __syncthreads();
-        const uint32_t q = x.tile_seg[g];
-        if (q != qcur) {
-            if (qcur != 0xFFFFFFFFu) flush(qcur);
-            qcur = q;
-            __syncthreads();
-        }
-        const fs_segment d = x.segs[list[q]];
-        const uint64_t t = g - x.tile_prefix[q];
-        const uint64_t b0 = t * kSegTile;
-        const uint32_t count = (uint32_t)((d.n - b0) < kSegTile ? (d.n - b0) : kSegTile);
-        const K* kin = static_cast<const K*>(d.keys_in) + b0;
-        for (uint32_t i = tid; i < count; i += kSegTileThreads) {
-            const K k = __builtin_nontemporal_load(&kin[i]);
-#pragma unroll
-            for (int j = 0; j < D; ++j) atomicAdd(&cnt[j][digit_of<K>(k, 8 * j)], 1u);
-        }
+        g = ge;
     }
-    __syncthreads();
-    if (qcur != 0xFFFFFFFFu) flush(qcur);
-    (void)s_q;
 }
 
 // per segment: exclusive scan of every digit in place, trivial digits,
@@ -347,11 +822,11 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegCtx x, int c) {
 }
 
 // one stable scatter pass over digit j for all large segments of the class
-template <typename K, typename V>
+// (tiles of 256 * ITEMS keys; the tile layout used the same size)
+template <typename K, typename V, int ITEMS>
 __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c, int j) {
     constexpr int W = kSegTileThreads / kWave;
-    constexpr int T = (int)kSegTile;
-    constexpr int ITEMS = kSegTileItems;
+    constexpr int T = kSegTileThreads * ITEMS;
     constexpr bool kHasVals = !__is_same(V, NoVal);
     using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
     __shared__ uint64_t s_peers[W][kRadix];
@@ -363,7 +838,6 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
     __shared__ VS s_vals[kHasVals ? T : 1];
 
     const uint32_t tiles = x.ctr[ctr_tiles(c)];
-    const uint32_t* list = x.large_list + (uint64_t)c * x.nseg;
     const uint32_t epoch = (uint32_t)(1 + 8 * c + j) << (kSegCountBits + 2);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int shift = 8 * j;
@@ -374,29 +848,30 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
         __syncthreads();
         if (tid == 0) s_ticket = add_agent(ticket, 1u);
         __syncthreads();
-        const uint32_t g = s_ticket;
+        const uint32_t g = __builtin_amdgcn_readfirstlane(s_ticket);
         if (g >= tiles) break;
-        const uint32_t q = x.tile_seg[g];
-        const uint32_t pl = x.plan[(uint64_t)q * 9 + j];
+        const SegTileDesc td = x.tdesc[g];  // one record: the segment and this pass's plan
+        const uint32_t pl = ((j < 4 ? td.plan[0] : td.plan[1]) >> (8 * (j & 3))) & 0xFFu;
         if (!(pl & 1u)) continue;  // trivial digit of this segment
-        const fs_segment d = x.segs[list[q]];
-        const uint32_t t = g - x.tile_prefix[q];
-        const uint32_t src = (pl >> 4) & 15u, dstsel = (pl >> 8) & 15u;
-        const uint64_t eo = x.elem_prefix[q];
-        const K* src_k = src == kBufIn ? static_cast<const K*>(d.keys_in)
-                       : src == kBufOut ? static_cast<const K*>(d.keys_out)
-                                        : reinterpret_cast<const K*>(x.tmp_k) + eo;
-        K* dst_k = dstsel == kBufOut ? static_cast<K*>(d.keys_out) : reinterpret_cast<K*>(x.tmp_k) + eo;
-        const VS* src_v = nullptr;
-        VS* dst_v = nullptr;
+        const uint32_t q = td.q, t = td.t;
+        const uint32_t src = (pl >> 1) & 3u, dstsel = (pl >> 3) & 3u;
+        const uint64_t eo = td.eo;
+        const auto src_k = to_global(src == kBufIn ? static_cast<const K*>(td.kin)
+                                     : src == kBufOut ? static_cast<const K*>(td.kout)
+                                                      : reinterpret_cast<const K*>(x.tmp_k) + eo);
+        const auto dst_k = to_global(dstsel == kBufOut ? static_cast<K*>(td.kout)
+                                                       : reinterpret_cast<K*>(x.tmp_k) + eo);
+        gptr<const VS> src_v = nullptr;
+        gptr<VS> dst_v = nullptr;
         if constexpr (kHasVals) {
-            src_v = src == kBufIn ? static_cast<const VS*>(d.vals_in)
-                  : src == kBufOut ? static_cast<const VS*>(d.vals_out)
-                                   : reinterpret_cast<const VS*>(x.tmp_v) + eo;
-            dst_v = dstsel == kBufOut ? static_cast<VS*>(d.vals_out) : reinterpret_cast<VS*>(x.tmp_v) + eo;
+            src_v = to_global(src == kBufIn ? static_cast<const VS*>(td.vin)
+                              : src == kBufOut ? static_cast<const VS*>(td.vout)
+                                               : reinterpret_cast<const VS*>(x.tmp_v) + eo);
+            dst_v = to_global(dstsel == kBufOut ? static_cast<VS*>(td.vout)
+                                                : reinterpret_cast<VS*>(x.tmp_v) + eo);
         }
         const uint64_t tb = (uint64_t)t * T;
-        const uint32_t count = (uint32_t)((d.n - tb) < (uint64_t)T ? (d.n - tb) : (uint64_t)T);
+        const uint32_t count = (uint32_t)((td.n - tb) < (uint64_t)T ? (td.n - tb) : (uint64_t)T);
         const uint32_t wbase = (uint32_t)wave * kWave * ITEMS;
         K key[ITEMS];
         VS val[ITEMS];
@@ -478,7 +953,7 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
             if (qq < count) {
                 const K kk = s_keys[qq];
                 const uint64_t o = s_delta[digit_of<K>(kk, shift)] + qq;
-                if (o < d.n) {
+                if (o < td.n) {
                     dst_k[o] = kk;
                     if constexpr (kHasVals) dst_v[o] = s_vals[qq];
                 } else {
@@ -486,6 +961,34 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
                 }
             }
         }
+    }
+}
+
+// one record per tile of the class's large segments (after the plans)
+__global__ void k_seg_tiledesc(SegCtx x, int c) {
+    const uint32_t tiles = x.ctr[ctr_tiles(c)];
+    const uint32_t* list = x.large_list + (uint64_t)c * x.nseg;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < tiles; g += gridDim.x * blockDim.x) {
+        const uint32_t q = x.tile_seg[g];
+        const fs_segment d = x.segs[list[q]];
+        SegTileDesc r;
+        r.kin = d.keys_in;
+        r.kout = d.keys_out;
+        r.vin = d.vals_in;
+        r.vout = d.vals_out;
+        r.n = d.n;
+        r.eo = x.elem_prefix[q];
+        r.q = q;
+        r.t = g - x.tile_prefix[q];
+        uint32_t pk[2] = {0u, 0u};
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t w = x.plan[(uint64_t)q * 9 + j];
+            const uint32_t b = (w & 1u) | (((w >> 4) & 3u) << 1) | (((w >> 8) & 3u) << 3);
+            pk[j >> 2] |= b << (8 * (j & 3));
+        }
+        r.plan[0] = pk[0];
+        r.plan[1] = pk[1];
+        x.tdesc[g] = r;
     }
 }
 
@@ -499,11 +1002,14 @@ __global__ __launch_bounds__(256) void k_seg_copy(SegCtx x, int c) {
         const uint32_t q = x.tile_seg[g];
         if (!x.plan[(uint64_t)q * 9 + 8]) continue;
         const fs_segment d = x.segs[list[q]];
-        const uint64_t tb = (uint64_t)(g - x.tile_prefix[q]) * kSegTile;
-        const uint64_t te = tb + kSegTile < d.n ? tb + kSegTile : d.n;
+        const uint64_t tb = (uint64_t)(g - x.tile_prefix[q]) * x.tile;
+        const uint64_t te = tb + x.tile < d.n ? tb + x.tile : d.n;
+        const auto kin = to_global(static_cast<const K*>(d.keys_in));
+        const auto kout = to_global(static_cast<K*>(d.keys_out));
         for (uint64_t i = tb + threadIdx.x; i < te; i += 256) {
-            static_cast<K*>(d.keys_out)[i] = static_cast<const K*>(d.keys_in)[i];
-            if constexpr (kHasVals) static_cast<V*>(d.vals_out)[i] = static_cast<const V*>(d.vals_in)[i];
+            kout[i] = kin[i];
+            if constexpr (kHasVals)
+                to_global(static_cast<V*>(d.vals_out))[i] = to_global(static_cast<const V*>(d.vals_in))[i];
         }
     }
 }
@@ -516,36 +1022,58 @@ __global__ void k_seg_zero_hist(SegCtx x, int c) {
 
 // ---------------------------------------------------------------------------
 template <typename K, typename V>
-static hipError_t run_class(const SegCtx& x, int c, int persistent, hipStream_t s) {
+static hipError_t run_class(const SegCtx& x, int c, int persistent, int items, hipStream_t s) {
     k_seg_zero_hist<<<1024, 256, 0, s>>>(x, c);
     k_seg_layout<<<1, 1024, 0, s>>>(x, c);
     k_seg_tilemap<<<256, 256, 0, s>>>(x, c);
     k_seg_hist<K><<<persistent, kSegTileThreads, 0, s>>>(x, c);
     k_seg_scan<K><<<persistent, 256, 0, s>>>(x, c);
-    for (int j = 0; j < (int)sizeof(K); ++j) k_seg_scatter<K, V><<<persistent, kSegTileThreads, 0, s>>>(x, c, j);
+    k_seg_tiledesc<<<256, 256, 0, s>>>(x, c);
+    for (int j = 0; j < (int)sizeof(K); ++j) {
+        if (items == 8) k_seg_scatter<K, V, 8><<<persistent, kSegTileThreads, 0, s>>>(x, c, j);
+        else k_seg_scatter<K, V, 16><<<persistent, kSegTileThreads, 0, s>>>(x, c, j);
+    }
     k_seg_copy<K, V><<<persistent, 256, 0, s>>>(x, c);
     return hipGetLastError();
 }
 
 uint32_t seg_max_tiles(uint64_t total_keys, uint32_t nseg) {
-    return (uint32_t)(total_keys / kSegTile + nseg + 1);
+    return (uint32_t)(total_keys / kSegMinTile + nseg + 1);
 }
 
-hipError_t launch_segmented(const SegCtx& x, hipStream_t s) {
+bool seg_tuning_valid(const fs_seg_tuning& t) {
+    return (t.tile_items == 8 || t.tile_items == 16) && t.large_wgs_per_cu >= 1 && t.large_wgs_per_cu <= 8 &&
+           t.small_wgs_per_cu >= 1 && t.small_wgs_per_cu <= 4 && t.expand16_wgs_per_cu >= 1 &&
+           t.expand16_wgs_per_cu <= 2;
+}
+
+hipError_t launch_segmented(const SegCtx& x0, const fs_seg_tuning& t, hipStream_t s) {
     const int cus = device_cu_count();
+    SegCtx x = x0;
+    x.tile = (uint32_t)kSegTileThreads * t.tile_items;
+    for (int w = 0; w < 3; ++w) x.small_max[w] = t.small_max_keys[w] < kSegMinSmallMax ? kSegMinSmallMax : t.small_max_keys[w];
+    x.expand_min = t.expand16_min_keys;
+    x.split_min = t.expand16_split_keys < kX16MinSplit ? kX16MinSplit : t.expand16_split_keys;
     k_seg_classify<<<(x.nseg + 255) / 256 < 1024 ? (x.nseg + 255) / 256 : 1024, 256, 0, s>>>(x);
-    k_seg_small<<<cus * 2, kSmallThreads, 0, s>>>(x);
-    const int P = cus * 2;
+    const int xg = cus * (int)t.expand16_wgs_per_cu;
+    k_seg_x16_layout<<<1, 1024, 0, s>>>(x);
+    k_seg_x16_zero<<<1024, 256, 0, s>>>(x);
+    k_seg_x16_hist<<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_x16_out<<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_expand16<<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_small<<<cus * (int)t.small_wgs_per_cu, kSmallThreads, 0, s>>>(x);
+    const int P = cus * (int)t.large_wgs_per_cu;
+    const int it = (int)t.tile_items;
     hipError_t e;
-    if ((e = run_class<uint16_t, NoVal>(x, 0, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint16_t, uint32_t>(x, 1, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint16_t, uint64_t>(x, 2, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, NoVal>(x, 3, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, uint32_t>(x, 4, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, uint64_t>(x, 5, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint64_t, NoVal>(x, 6, P, s)) != hipSuccess) return e;
-    if ((e = run_class<uint64_t, uint32_t>(x, 7, P, s)) != hipSuccess) return e;
-    return run_class<uint64_t, uint64_t>(x, 8, P, s);
+    if ((e = run_class<uint16_t, NoVal>(x, 0, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint16_t, uint32_t>(x, 1, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint16_t, uint64_t>(x, 2, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, NoVal>(x, 3, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, uint32_t>(x, 4, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, uint64_t>(x, 5, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint64_t, NoVal>(x, 6, P, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint64_t, uint32_t>(x, 7, P, it, s)) != hipSuccess) return e;
+    return run_class<uint64_t, uint64_t>(x, 8, P, it, s);
 }
 
 }  // namespace fs

@@ -147,3 +147,98 @@ def test_graph_replays_match_eager(gpu):
         assert ws.error_word() == 0
         check(host, devs)
         del junk
+
+
+# ---- launch tunings: every bin choice gives the same bits -------------------
+
+NEVER = 0xFFFFFFFF
+TUNINGS = [
+    None,  # process-wide default
+    {"small_max_keys": [NEVER] * 3, "expand16_min_keys": NEVER, "expand16_split_keys": NEVER,
+     "expand16_wgs_per_cu": 1, "tile_items": 16, "large_wgs_per_cu": 2,
+     "small_wgs_per_cu": 2},  # 8-bit digits everywhere
+    {"small_max_keys": [1024, 1024, 1024], "expand16_min_keys": 1, "expand16_split_keys": 1 << 18,
+     "expand16_wgs_per_cu": 2, "tile_items": 8, "large_wgs_per_cu": 8,
+     "small_wgs_per_cu": 1},  # every 16-bit keys-only segment expanded, long ones split
+    {"small_max_keys": [4096, 2048, NEVER], "expand16_min_keys": 65536, "expand16_split_keys": NEVER,
+     "expand16_wgs_per_cu": 1, "tile_items": 8, "large_wgs_per_cu": 1,
+     "small_wgs_per_cu": 4},  # long ones on one workgroup each
+]
+
+
+def tuned_batch(gpu):
+    """16-bit keys-only segments on both sides of 65536 keys (where packed
+    counters can carry), with skewed and all-equal keys whose bins pass
+    65535, slices at odd element offsets (unaligned starts and ends), plus
+    other widths for the other bins."""
+    host, devs = [], []
+    big = torch.from_numpy(fsgen.keys_host("uniform", 16, 300007, 77)).to(gpu)
+    big_out = torch.full_like(big.view(torch.int16), 0xBEEF - 0x10000).view(torch.uint16)
+    spec = [(1, "uniform"), (7, "uniform"), (1000, "zipf"), (4095, "uniform"), (9000, "gaussian"),
+            (65535, "equal"), (65536, "zipf"), (70001, "uniform"), (200003, "zipf"),
+            ((1 << 18) + 5, "uniform"), (3 * (1 << 18) + 1001, "zipf"), (1 << 20, "equal")]
+    for i, (n, dist) in enumerate(spec):
+        h, d = make_segment(n, 16, 0, dist, fsgen.seed_for(7, i), gpu)
+        host.append(h)
+        devs.append(d)
+    # every key the same odd or even value: a low-half carry each 65536 keys,
+    # and for the odd value carries out of the whole word
+    for val, n in ((0x1234, 150001), (0x4321, 150001), (0xFFFF, 150001), (0, 150001), (0x7777, 600000)):
+        k = np.full(n, val, dtype=np.uint16)
+        kd = torch.from_numpy(k).to(gpu)
+        host.append((k, None))
+        devs.append((kd, torch.empty_like(kd), None, None))
+    # two neighbouring values sharing one counter word
+    k = np.where(np.arange(140000) % 3 == 0, 0x4444, 0x4445).astype(np.uint16)
+    kd = torch.from_numpy(k).to(gpu)
+    host.append((k, None))
+    devs.append((kd, torch.empty_like(kd), None, None))
+    # unaligned slices of one array (starts and ends inside 16-byte blocks)
+    slices = ((1, 40000), (40003, 40013), (40021, 140021), (140029, 300000))
+    for a, b in slices:
+        host.append((big[a:b].cpu().numpy(), None))
+        devs.append((big[a:b], big_out[a:b], None, None))
+    # elements of big_out outside every slice must keep their fill
+    gaps = [(0, 1), (40000, 40003), (40013, 40021), (140021, 140029), (300000, 300007)]
+    for i, (n, bits, vb) in enumerate([(3000, 32, 0), (20000, 32, 4), (50000, 64, 0), (9000, 16, 4),
+                                       (100000, 32, 0), (5000, 64, 8)]):
+        h, d = make_segment(n, bits, vb, "uniform", fsgen.seed_for(8, i), gpu)
+        host.append(h)
+        devs.append(d)
+    return host, devs, (big_out, gaps)
+
+
+def check_gaps(guard):
+    out, gaps = guard
+    o = out.cpu().numpy()
+    for a, b in gaps:
+        assert (o[a:b] == 0xBEEF).all(), (a, b)
+
+
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+def test_every_tuning_is_bit_exact(gpu, ti):
+    host, devs, guard = tuned_batch(gpu)
+    t = fs.SegTuning.from_dict(TUNINGS[ti]) if TUNINGS[ti] else None
+    ws = fs.sort_segmented(devs, tuning=t)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    check(host, devs)
+    check_gaps(guard)
+
+
+def test_autotuner_picks_a_valid_tuning(gpu):
+    from paper_2605_10390_amd import autotune
+    host, devs, guard = tuned_batch(gpu)
+    batch = fs.SegmentBatch(devs)
+    ws = fs.Workspace(gpu)
+    best, report = autotune.tune_batch(batch, ws, reps=1, sweeps=1)
+    assert report["best_ms"] <= report["start_ms"]
+    signed = {2: torch.int16, 4: torch.int32, 8: torch.int64}
+    for d in devs:
+        for t in (d[1], d[3]):
+            if t is not None and t.numel():
+                t.view(signed[t.element_size()]).zero_()
+    batch.run(ws, tuning=best)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    check(host, devs)
