@@ -59,24 +59,39 @@ def scatter_bytes_per_key(key_bits, val_bytes):
     return 2 * (key_bits // 8 + val_bytes)
 
 
-def scatter_bytes_per_launch_key(key_bits, val_bytes, passes):
-    """Average algorithmic bytes per key of one scatter launch.  A 16-bit
-    pair sort's last pass writes only the payloads (its keys are expanded
+def active_digits(keys, key_bits):
+    """Which 8-bit digits are not trivial (not shared by every key); the sort
+    skips the trivial ones on the device, so only these passes move data."""
+    import torch
+    kk = keys.view({16: torch.int16, 32: torch.int32, 64: torch.int64}[key_bits])
+    out = []
+    for j in range(key_bits // 8):
+        d = (kk >> (8 * j)) & 0xFF
+        out.append(bool(d.min() != d.max()))
+    return out
+
+
+def scatter_pass_bytes(key_bits, val_bytes, active):
+    """Algorithmic bytes per key of every scatter pass that runs.  A 16-bit
+    pair sort's second pass writes only the payloads (its keys are expanded
     from the 16-bit histogram), so it moves kb bytes per key fewer."""
-    full = scatter_bytes_per_key(key_bits, val_bytes)
-    if key_bits == 16 and val_bytes and passes:
-        return (passes * full - key_bits // 8) / passes
-    return full
+    kb, full = key_bits // 8, scatter_bytes_per_key(key_bits, val_bytes)
+    return [full - (kb if key_bits == 16 and val_bytes and j == 1 else 0)
+            for j, a in enumerate(active) if a]
 
 
-def algorithmic_bytes_per_key(key_bits, val_bytes, passes):
+def algorithmic_bytes_per_key(key_bits, val_bytes, active):
     """Whole sort: one read of the keys for the histograms, then every pass
-    reads and writes key + payload; a 16-bit keys-only sort is one read plus
-    one write of the keys (expansion).  For 16-bit pairs the last pass's key
-    write is replaced by the expansion's: the same bytes."""
+    that runs reads and writes key + payload; a 16-bit keys-only sort is one
+    read plus one write of the keys (expansion).  For 16-bit pairs the second
+    pass's key write is replaced by the expansion's: the same bytes.  With no
+    pass to run, the sort is the histogram read plus a copy."""
     kb = key_bits // 8
     if key_bits == 16 and val_bytes == 0:
         return 2 * kb
+    passes = sum(active)
+    if passes == 0:
+        return kb + 2 * (kb + val_bytes)
     return kb + passes * scatter_bytes_per_key(key_bits, val_bytes)
 
 
@@ -340,6 +355,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4"])
     ap.add_argument("--jobs", type=int, default=1000, help="served-stream prefix length (c4)")
+    ap.add_argument("--dist", default=None,
+                    help="c0/c1/c2a/c2b: key distribution (16-bit: uniform gaussian zipf equal presorted "
+                         "reverse; wider: uniform small20 hot90); default uniform")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="c3: default launch tuning")
     ap.add_argument("--no-loop-baseline", action="store_true",
@@ -370,9 +388,16 @@ def main():
     import paper_2605_10390_amd as fs
 
     key_bits, val_bytes, logn, dist, desc = WORKLOADS[args.workload]
+    if args.dist is not None:
+        if args.dist not in fsgen.valid_dists(key_bits):
+            raise SystemExit(f"--dist {args.dist}: not a {key_bits}-bit distribution "
+                             f"({', '.join(fsgen.valid_dists(key_bits))})")
+        desc = desc.replace(f", {dist}", f", {args.dist}")
+        dist = args.dist
     n = 1 << logn
     dev = torch.device("cuda:0")
-    seed = fsgen.seed_for({"c0": 0, "c1": 1, "c2a": 2, "c2b": 2}[args.workload], 0)
+    seed = fsgen.seed_for({"c0": 0, "c1": 1, "c2a": 2, "c2b": 2}[args.workload],
+                          fsgen.valid_dists(key_bits).index(dist))
     keys = fsgen.keys_device(dist, key_bits, n, seed, device=dev)
     vals = fsgen.index_device(n, val_bytes, device=dev) if val_bytes else None
     if args.copy_probe:  # counter calibration: a plain copy of known size
@@ -434,27 +459,31 @@ def main():
 
     ms_step = ms_total / args.steps
     gkeys = n * args.steps / (ms_total / 1e3) / 1e9
-    sc = kernels["scatter"]
-    passes = (sc["launches"] and round(sc["keys"] / args.steps / n)) or 0
-    bpk = algorithmic_bytes_per_key(key_bits, val_bytes, passes)
+    active = active_digits(keys, key_bits)
+    pass_bytes = scatter_pass_bytes(key_bits, val_bytes, active) if not (key_bits == 16 and val_bytes == 0) else []
+    passes = len(pass_bytes)
+    bpk = algorithmic_bytes_per_key(key_bits, val_bytes, active)
+    scatter_avg = sum(pass_bytes) / passes if passes else 0
     for name, kinfo in kernels.items():
         if kinfo["launches"]:
             kinfo["ms_avg"] = kinfo["ms_total"] / kinfo["launches"]
-            per_key = {"histogram": key_bits // 8,
-                       "scatter": scatter_bytes_per_launch_key(key_bits, val_bytes, passes),
-                       "expand": key_bits // 8}.get(name)
-            if per_key and kinfo["ms_total"] > 0:
-                kinfo["gbps"] = kinfo["keys"] * per_key / (kinfo["ms_total"] / 1e3) / 1e9
     dom_name = DOMINANT[args.workload]
     if key_bits == 16 and val_bytes == 0:
         dom = kernels["expand"]
         dom_bytes_per_key = 2  # the expansion writes every key once
+        dom_bytes_step = n * 2
     else:
+        # every scatter launch is timed, also those whose digit the device
+        # found trivial (they exit at once); the bytes are those of the passes
+        # that run, the time is all of it
         dom = kernels["scatter"]
-        dom_bytes_per_key = scatter_bytes_per_launch_key(key_bits, val_bytes, passes)
-    achieved = (dom["keys"] / dom["launches"]) * dom_bytes_per_key / (dom["ms_avg"] / 1e3) / 1e9
+        dom_bytes_per_key = scatter_avg
+        dom_bytes_step = n * sum(pass_bytes)
+    dom_ms_step = dom["ms_total"] / args.steps
+    # with every digit trivial (all-equal keys) no pass runs: no dominant-kernel figure
+    achieved = dom_bytes_step / (dom_ms_step / 1e3) / 1e9 if dom_bytes_step and dom_ms_step > 0 else None
     src_hash = kernel_source_hash()
-    traffic = read_traffic(src_hash) if args.workload == "c1" else None
+    traffic = read_traffic(src_hash) if args.workload == "c1" and dist == "uniform" else None
     out = {
         "metric": METRIC,
         "value": round(gkeys, 3),
@@ -470,10 +499,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "key_bits": key_bits, "val_bytes": val_bytes,
                    "distribution": dist, "seed": seed, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "roofline": {"bound": "hbm", "kernel": dom_name if achieved else None,
+                     "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
                      "traffic": traffic, "bytes_per_key": dom_bytes_per_key,
-                     "keys_per_launch": dom["keys"] // max(dom["launches"], 1)},
+                     "keys_per_launch": dom["keys"] // max(dom["launches"], 1),
+                     "active_digits": [int(a) for a in active]},
         "hbm_frac_whole_sort": round(n * bpk / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes_per_key": bpk,
         "kernels": {k: {kk2: (round(vv, 4) if isinstance(vv, float) else vv) for kk2, vv in v.items()}

@@ -145,9 +145,15 @@ fs_status fs_sort_segmented(const fs_segment *d_segments, uint32_t num_segments,
  *                      values below 2^18 are raised to 2^18, 0xFFFFFFFF
  *                      never splits.
  *   expand16_wgs_per_cu  workgroups per compute unit of that bin, 1..2.
- *   tile_items         the remaining (large) segments are sorted with 8-bit
- *                      digits by many workgroups, in tiles of
- *                      256 * tile_items keys; tile_items is 8 or 16.
+ *   large_wg_max_keys  remaining segments of at most this many keys are
+ *                      sorted by ONE workgroup each, with 8-bit digits and
+ *                      passes through global memory (tiles of 256 *
+ *                      tile_items keys walked in order; no look-back).  0
+ *                      disables it.
+ *   tile_items, tile_threads  the remaining (large) segments are sorted
+ *                      with 8-bit digits by many workgroups, in tiles of
+ *                      tile_threads * tile_items keys; tile_items is 8 or
+ *                      16, tile_threads (the workgroup size) 256 or 512.
  *   large_wgs_per_cu   workgroups per compute unit of the large-segment
  *                      histogram and scatter launches, 1..8.
  *   small_wgs_per_cu   workgroups per compute unit of the LDS bin, 1..4.
@@ -158,7 +164,9 @@ typedef struct {
     uint32_t expand16_min_keys;
     uint32_t expand16_split_keys;
     uint32_t expand16_wgs_per_cu;
+    uint32_t large_wg_max_keys;
     uint32_t tile_items;
+    uint32_t tile_threads;
     uint32_t large_wgs_per_cu;
     uint32_t small_wgs_per_cu;
 } fs_seg_tuning;

@@ -210,11 +210,14 @@ class SegTuning(ctypes.Structure):
     width via the 16-bit-digit bin, tile size, workgroups per CU)."""
     _fields_ = [("small_max_keys", ctypes.c_uint32 * 3), ("expand16_min_keys", ctypes.c_uint32),
                 ("expand16_split_keys", ctypes.c_uint32), ("expand16_wgs_per_cu", ctypes.c_uint32),
-                ("tile_items", ctypes.c_uint32), ("large_wgs_per_cu", ctypes.c_uint32),
+                ("large_wg_max_keys", ctypes.c_uint32),
+                ("tile_items", ctypes.c_uint32), ("tile_threads", ctypes.c_uint32),
+                ("large_wgs_per_cu", ctypes.c_uint32),
                 ("small_wgs_per_cu", ctypes.c_uint32)]
 
     FIELDS = ("small_max_keys", "expand16_min_keys", "expand16_split_keys", "expand16_wgs_per_cu",
-              "tile_items", "large_wgs_per_cu", "small_wgs_per_cu")
+              "large_wg_max_keys",
+              "tile_items", "tile_threads", "large_wgs_per_cu", "small_wgs_per_cu")
 
     def as_dict(self):
         d = {f: getattr(self, f) for f in self.FIELDS}

@@ -10,7 +10,7 @@ Segments are binned on the device by width and length, and a tuning
   - how many workgroups sort one segment: one (the LDS bin, up to
     `small_max_keys[w]` keys, or the 16-bit-digit bin) or many (the large
     bin, in tiles);
-  - the tile size of the large bin (`tile_items`) and the workgroups per
+  - the tile size of the large bin (`tile_items` x `tile_threads`) and the workgroups per
     compute unit of the LDS and large bins.
 Every tuning gives bit-identical output, so the tuner only times.
 
@@ -36,14 +36,17 @@ CANDIDATES = {
     "small_max_keys.0": [1024, 2048, 4096, 8192, NEVER],
     "small_max_keys.1": [1024, 2048, 4096, NEVER],
     "small_max_keys.2": [1024, 2048, NEVER],
+    "large_wg_max_keys": [0, 1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21],
     "tile_items": [8, 16],
+    "tile_threads": [256, 512],
     "large_wgs_per_cu": [1, 2, 3, 4, 6, 8],
     "small_wgs_per_cu": [1, 2],
 }
 # search order; a tuple is a group of coupled fields searched over their
 # product (the tile size decides how many workgroups fit on a CU)
 ORDER = ["expand16_min_keys", "expand16_split_keys", "expand16_wgs_per_cu", "small_max_keys.0",
-         "small_max_keys.1", "small_max_keys.2", ("tile_items", "large_wgs_per_cu"), "small_wgs_per_cu"]
+         "small_max_keys.1", "small_max_keys.2", "large_wg_max_keys",
+         ("tile_items", "tile_threads", "large_wgs_per_cu"), "small_wgs_per_cu"]
 
 
 def get_field(t, name):

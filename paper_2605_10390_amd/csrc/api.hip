@@ -281,9 +281,10 @@ namespace {
 // built-in defaults (what the autotuner picked for a log-normal mix of
 // 16- and 32-bit segments on MI355X): the LDS bin takes whatever fits,
 // 16-bit keys-only segments from 16384 keys take the 16-bit-digit bin (split
-// from 2^18 keys), tiles of 4096 keys, three workgroups per CU in the large
-// bin and two in the LDS bin
-constexpr fs_seg_tuning kDefaultTuning = {{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, 16384u, 1u << 18, 1u, 16u, 3u, 2u};
+// from 2^18 keys, two workgroups per CU), other segments up to 2^17 keys get
+// one workgroup each, tiles of 4096 keys, three workgroups per CU in the
+// large bin and two in the LDS bin
+constexpr fs_seg_tuning kDefaultTuning = {{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, 16384u, 1u << 18, 2u, 1u << 17, 16u, 256u, 3u, 2u};
 std::mutex g_tuning_mu;
 fs_seg_tuning g_tuning = kDefaultTuning;
 }  // namespace
@@ -340,13 +341,14 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
         off = align_up(off + std::max<size_t>(bytes, 1), 256);
         return o;
     };
-    const size_t o_err = take(4 * (1 + 128));
+    const size_t o_err = take(4 * (1 + 256));
     const size_t o_small = take(4ull * nseg);
     const size_t o_expand = take(4ull * nseg);
     const uint64_t nx_max = std::min<uint64_t>(nseg, total_keys / kX16MinSplit);
     const size_t o_x16p = take(4ull * (nx_max + 1));
     const size_t o_x16h = take(4ull * 65536 * nx_max);
     const size_t o_large = take(4ull * 9 * nseg);
+    const size_t o_wg = take(4ull * 9 * nseg);
     const size_t o_tp = take(4ull * (nseg + 1));
     const size_t o_ep = take(8ull * (nseg + 1));
     const size_t o_ts = take(4ull * max_tiles);
@@ -379,6 +381,7 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
     x.x16_parts = reinterpret_cast<uint32_t*>(w + o_x16p);
     x.x16_hist = reinterpret_cast<uint32_t*>(w + o_x16h);
     x.large_list = reinterpret_cast<uint32_t*>(w + o_large);
+    x.wg_list = reinterpret_cast<uint32_t*>(w + o_wg);
     x.tile_prefix = reinterpret_cast<uint32_t*>(w + o_tp);
     x.elem_prefix = reinterpret_cast<uint64_t*>(w + o_ep);
     x.tile_seg = reinterpret_cast<uint32_t*>(w + o_ts);
@@ -388,7 +391,7 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
     x.tdesc = reinterpret_cast<SegTileDesc*>(w + o_tdesc);
     x.tmp_k = w + o_tk;
     x.tmp_v = w + o_tv;
-    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.err, 1 + 128, 0, s));
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.err, 1 + 256, 0, s));
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.state, (uint64_t)max_tiles * kRadix, 0, s));
     FS_LAUNCH(FS_KERNEL_SEGMENTED, total_keys, launch_segmented(x, tune, s));
     return FS_OK;

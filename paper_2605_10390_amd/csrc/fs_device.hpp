@@ -142,4 +142,23 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint64_t* 
     return before + below;
 }
 
+// wave_rank with a fast path for a wave whose valid lanes all hold the same
+// digit (presorted, reverse-sorted or hot-key input): the rank is then the
+// lane's position among the valid lanes, and the LDS word every lane would
+// OR into (a 64-way same-address conflict) is not touched.
+__device__ __forceinline__ uint32_t wave_rank_uniform_first(uint32_t d, bool valid, uint64_t* peers_w,
+                                                            uint32_t* cnt_w) {
+    const uint64_t vm = ballot(valid);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xFFFFFFFFu);
+    if (vm != 0 && ballot(valid && d == d0) == vm) {
+        const uint32_t before = cnt_w[d0];
+        const uint32_t below = lanes_below(vm);
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) cnt_w[d0] = before + popc64(vm);
+        __builtin_amdgcn_wave_barrier();
+        return before + below;
+    }
+    return wave_rank(d, valid, peers_w, cnt_w);
+}
+
 }  // namespace fs

@@ -141,6 +141,7 @@ struct SegCtx {
     uint32_t small_max[3];  // per key width: longest segment of the LDS bin
     uint32_t expand_min;    // 16-bit keys-only segments this long take the 16-bit-digit bin
     uint32_t split_min;     //   and from this long get several workgroups
+    uint32_t wg_max;        // large segments up to this long get one workgroup each
     uint32_t* err;
     uint32_t* ctr;          // queue counters, tile totals, tickets
     uint32_t* small_list;   // [nseg]
@@ -148,6 +149,7 @@ struct SegCtx {
     uint32_t* x16_parts;    // [long segments + 1] part prefix
     uint32_t* x16_hist;     // [long segments][65536] exact bin counts
     uint32_t* large_list;   // [9][nseg]
+    uint32_t* wg_list;      // [9][nseg]
     uint32_t* tile_prefix;  // [nseg + 1] (current class)
     uint64_t* elem_prefix;  // [nseg + 1] (current class)
     uint32_t* tile_seg;     // [max_tiles]

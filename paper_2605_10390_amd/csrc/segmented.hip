@@ -50,6 +50,9 @@ __host__ __device__ inline int ctr_expand_long() { return 121; }  // 16-bit-digi
 __host__ __device__ inline int ctr_expand_rest() { return 122; }  //   other segments queued
 __host__ __device__ inline int ctr_expand_taken() { return 123; }
 __host__ __device__ inline int ctr_x16_parts() { return 124; }  // parts of the long segments
+__host__ __device__ inline int ctr_wg(int c) { return 128 + c; }        // one-workgroup large segments queued
+__host__ __device__ inline int ctr_wg_taken(int c) { return 137 + c; }  //   and taken
+__host__ __device__ inline int ctr_wg_tmp(int c) { return 147 + 2 * c; }  // 64-bit temporary-pool bump (8-byte aligned)
 
 // ---------------------------------------------------------------------------
 __global__ void k_seg_classify(SegCtx x) {
@@ -83,6 +86,10 @@ __global__ void k_seg_classify(SegCtx x) {
         } else if (d.n <= small_cap(kb, vb) && d.n <= small_max) {
             const uint32_t i = atomicAdd(&x.ctr[0], 1u);
             x.small_list[i] = s;
+        } else if (d.n <= x.wg_max) {
+            const int c = seg_class(kb, vb);
+            const uint32_t i = atomicAdd(&x.ctr[ctr_wg(c)], 1u);
+            x.wg_list[(uint64_t)c * x.nseg + i] = s;
         } else {
             const int c = seg_class(kb, vb);
             const uint32_t i = atomicAdd(&x.ctr[ctr_large(c)], 1u);
@@ -822,11 +829,13 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegCtx x, int c) {
 }
 
 // one stable scatter pass over digit j for all large segments of the class
-// (tiles of 256 * ITEMS keys; the tile layout used the same size)
-template <typename K, typename V, int ITEMS>
-__global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c, int j) {
-    constexpr int W = kSegTileThreads / kWave;
-    constexpr int T = kSegTileThreads * ITEMS;
+// (tiles of THREADS * ITEMS keys; the tile layout used the same size).  The
+// first 256 threads also own one digit value each for the tile's counts,
+// its look-back and its output offsets.
+template <typename K, typename V, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_seg_scatter(SegCtx x, int c, int j) {
+    constexpr int W = THREADS / kWave;
+    constexpr int T = THREADS * ITEMS;
     constexpr bool kHasVals = !__is_same(V, NoVal);
     using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
     __shared__ uint64_t s_peers[W][kRadix];
@@ -841,8 +850,10 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
     const uint32_t epoch = (uint32_t)(1 + 8 * c + j) << (kSegCountBits + 2);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int shift = 8 * j;
-    for (int i = tid; i < W * kRadix; i += kSegTileThreads) (&s_peers[0][0])[i] = 0;
+    for (int i = tid; i < W * kRadix; i += THREADS) (&s_peers[0][0])[i] = 0;
     uint32_t* ticket = &x.ctr[ctr_ticket(c, j)];
+    const bool owner = tid < kRadix;  // owns digit value b = tid
+    const int b = owner ? tid : 0;
 
     for (;;) {
         __syncthreads();
@@ -877,11 +888,11 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
         VS val[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
+            // every lane loads (clamped into the tile), so no load waits on a branch
             const uint32_t idx = wbase + k * kWave + lane;
-            if (idx < count) {
-                key[k] = src_k[tb + idx];
-                if constexpr (kHasVals) val[k] = src_v[tb + idx];
-            }
+            const uint32_t ic = idx < count ? idx : count - 1;
+            key[k] = src_k[tb + ic];
+            if constexpr (kHasVals) val[k] = src_v[tb + ic];
         }
         for (int i = 0; i < kRadix / kWave; ++i) s_wcnt[wave][lane + kWave * i] = 0;
         __builtin_amdgcn_wave_barrier();
@@ -892,14 +903,14 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
             rank[k] = wave_rank(digit_of<K>(key[k], shift), valid, s_peers[wave], s_wcnt[wave]);
         }
         __syncthreads();
-        const int b = tid;
         uint32_t h = 0;
-        for (int w = 0; w < W; ++w) h += s_wcnt[w][b];
+        if (owner)
+            for (int w = 0; w < W; ++w) h += s_wcnt[w][b];
         uint32_t* st = x.state + (uint64_t)g * kRadix;
-        st_agent(&st[b], epoch | (t == 0 ? kSegPrefix : kSegAgg) | h);
+        if (owner) st_agent(&st[b], epoch | (t == 0 ? kSegPrefix : kSegAgg) | h);
         uint64_t tot;
         const uint32_t start = (uint32_t)scan256_exclusive<uint64_t>(h, s_wsum, &tot);
-        {
+        if (owner) {
             uint32_t r = start;
             for (int w = 0; w < W; ++w) {
                 const uint32_t cc = s_wcnt[w][b];
@@ -908,7 +919,7 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
             }
         }
         uint32_t excl = 0;
-        if (t > 0) {
+        if (owner && t > 0) {
             int64_t p = (int64_t)g - 1;
             const int64_t first = (int64_t)g - t;  // tile 0 of this segment
             uint32_t spins = 0;
@@ -931,8 +942,10 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
             }
             st_agent(&st[b], epoch | kSegPrefix | (excl + h));
         }
-        const uint64_t gb = (uint64_t)x.hist[(uint64_t)q * 8 * kRadix + j * kRadix + b] + excl;
-        s_delta[b] = gb - start;
+        if (owner) {
+            const uint64_t gb = (uint64_t)x.hist[(uint64_t)q * 8 * kRadix + j * kRadix + b] + excl;
+            s_delta[b] = gb - start;
+        }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
@@ -949,7 +962,7 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t qq = k * kSegTileThreads + tid;
+            const uint32_t qq = k * THREADS + tid;
             if (qq < count) {
                 const K kk = s_keys[qq];
                 const uint64_t o = s_delta[digit_of<K>(kk, shift)] + qq;
@@ -960,6 +973,200 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_scatter(SegCtx x, int c
                     atomicOr(x.err, 8u);
                 }
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large segments of at most wg_max keys: one workgroup per segment, passes
+// through global memory.  The workgroup owns the whole segment, so a pass
+// walks the tiles in input order and carries each digit value's next output
+// position from tile to tile in LDS: the stable scatter needs no look-back
+// and no workgroup waits for another.
+// ---------------------------------------------------------------------------
+template <typename K, typename V, int ITEMS>
+__global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
+    constexpr int THREADS = 256;
+    constexpr int W = THREADS / kWave;
+    constexpr int T = THREADS * ITEMS;
+    constexpr int D = sizeof(K);
+    constexpr int VK = 16 / (int)sizeof(K);
+    constexpr bool kHasVals = !__is_same(V, NoVal);
+    using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
+    __shared__ uint64_t s_peers[W][kRadix];
+    __shared__ uint32_t s_wcnt[W][kRadix];
+    __shared__ uint32_t s_start[D][kRadix];  // digit histograms, then their exclusive prefixes
+    __shared__ uint32_t s_next[kRadix];      // next output position of each digit value in this pass
+    __shared__ uint32_t s_delta[kRadix];     // output position minus staged position, this tile
+    __shared__ uint64_t s_wsum[4];
+    __shared__ uint32_t s_trivial[D];
+    __shared__ uint32_t s_item, s_next_item;
+    __shared__ unsigned long long s_eo;
+    __shared__ K s_keys[T];
+    __shared__ VS s_vals[kHasVals ? T : 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t cnt = x.ctr[ctr_wg(c)];
+    const uint32_t* list = x.wg_list + (uint64_t)c * x.nseg;
+    uint32_t* taken = &x.ctr[ctr_wg_taken(c)];
+    for (int i = tid; i < W * kRadix; i += THREADS) (&s_peers[0][0])[i] = 0;
+    if (tid == 0) s_next_item = add_agent(taken, 1u);
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            s_item = s_next_item;
+            if (s_item < cnt) s_next_item = add_agent(taken, 1u);
+        }
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= cnt) break;
+        const fs_segment d = x.segs[list[item]];
+        const uint32_t n = (uint32_t)d.n;
+        if (tid == 0)
+            s_eo = atomicAdd(reinterpret_cast<unsigned long long*>(&x.ctr[ctr_wg_tmp(c)]), (unsigned long long)n);
+        for (int i = tid; i < D * kRadix; i += THREADS) (&s_start[0][0])[i] = 0;
+        __syncthreads();
+        // 1. every digit's histogram in one read (aligned 16-byte vectors,
+        //    elements outside the segment masked; wave-uniform digits added once)
+        {
+            const uintptr_t p = reinterpret_cast<uintptr_t>(d.keys_in);
+            const uintptr_t a0 = p & ~(uintptr_t)15;
+            const uint32_t lead = (uint32_t)((p - a0) / sizeof(K));
+            const uint32_t nv = (lead + n + VK - 1) / VK;
+            const gptr<const u32x4> vp = (gptr<const u32x4>)(a0);
+            constexpr int U = 4;
+            for (uint32_t i0 = 0; i0 < nv; i0 += U * THREADS) {
+                u32x4 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t i = i0 + u * THREADS + tid;
+                    v[u] = __builtin_nontemporal_load(&vp[i < nv ? i : nv - 1]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t i = i0 + u * THREADS + tid;
+                    const K* kv = reinterpret_cast<const K*>(&v[u]);
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const uint32_t idx = i * VK + e;
+                        const bool valid = i < nv && idx >= lead && idx < lead + n;
+#pragma unroll
+                        for (int j = 0; j < D; ++j) {
+                            const uint32_t dg = digit_of<K>(kv[e], 8 * j);
+                            const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                            const uint64_t act = ballot(valid);
+                            if (act != 0 && ballot(valid && dg == d0) == act) {
+                                if (lanes_below(act) == 0 && valid) atomicAdd(&s_start[j][dg], popc64(act));
+                            } else if (valid) {
+                                atomicAdd(&s_start[j][dg], 1u);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // 2. exclusive prefix of every digit; trivial digits
+        for (int j = 0; j < D; ++j) {
+            const uint32_t h = s_start[j][tid];
+            uint64_t tot;
+            const uint32_t e = (uint32_t)scan256_exclusive<uint64_t>(h, s_wsum, &tot);
+            s_start[j][tid] = e;
+            const int triv = __syncthreads_or(h == n);
+            if (tid == 0) s_trivial[j] = triv;
+        }
+        __syncthreads();
+        int active = 0;
+        for (int j = 0; j < D; ++j) active += s_trivial[j] ? 0 : 1;
+        if (active == 0) {  // already sorted: the output is the input
+            for (uint32_t i = tid; i < n; i += THREADS) {
+                to_global(static_cast<K*>(d.keys_out))[i] = to_global(static_cast<const K*>(d.keys_in))[i];
+                if constexpr (kHasVals)
+                    to_global(static_cast<VS*>(d.vals_out))[i] = to_global(static_cast<const VS*>(d.vals_in))[i];
+            }
+            continue;
+        }
+        // 3. the passes, ping-ponging so that the last one writes the output
+        const uint64_t eo = s_eo;
+        const K* src_k = static_cast<const K*>(d.keys_in);
+        const VS* src_v = kHasVals ? static_cast<const VS*>(d.vals_in) : nullptr;
+        int done = 0;
+        for (int j = 0; j < D; ++j) {
+            if (s_trivial[j]) continue;
+            const bool to_out = (active - 1 - done) % 2 == 0;
+            K* dst_k = to_out ? static_cast<K*>(d.keys_out) : reinterpret_cast<K*>(x.tmp_k) + eo;
+            VS* dst_v = nullptr;
+            if constexpr (kHasVals) dst_v = to_out ? static_cast<VS*>(d.vals_out) : reinterpret_cast<VS*>(x.tmp_v) + eo;
+            const int shift = 8 * j;
+            s_next[tid] = s_start[j][tid];
+            for (uint32_t tb = 0; tb < n; tb += T) {
+                const uint32_t count = n - tb < (uint32_t)T ? n - tb : (uint32_t)T;
+                const uint32_t wbase = (uint32_t)wave * kWave * ITEMS;
+                K key[ITEMS];
+                VS val[ITEMS];
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const uint32_t idx = wbase + k * kWave + lane;
+                    const uint32_t ic = idx < count ? idx : count - 1;
+                    key[k] = to_global(src_k)[tb + ic];
+                    if constexpr (kHasVals) val[k] = to_global(src_v)[tb + ic];
+                }
+                for (int i = 0; i < kRadix / kWave; ++i) s_wcnt[wave][lane + kWave * i] = 0;
+                __builtin_amdgcn_wave_barrier();
+                uint32_t rank[ITEMS];
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const bool valid = wbase + k * kWave + lane < count;
+                    rank[k] = wave_rank(digit_of<K>(key[k], shift), valid, s_peers[wave], s_wcnt[wave]);
+                }
+                __syncthreads();
+                uint32_t h = 0;
+                for (int w = 0; w < W; ++w) h += s_wcnt[w][tid];
+                uint64_t tot;
+                const uint32_t start = (uint32_t)scan256_exclusive<uint64_t>(h, s_wsum, &tot);
+                {
+                    uint32_t r = start;
+                    for (int w = 0; w < W; ++w) {
+                        const uint32_t cc = s_wcnt[w][tid];
+                        s_wcnt[w][tid] = r;
+                        r += cc;
+                    }
+                }
+                s_delta[tid] = s_next[tid] - start;  // modulo 2^32; positions stay below n
+                s_next[tid] += h;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    if (wbase + k * kWave + lane < count) {
+                        const uint32_t pos = s_wcnt[wave][digit_of<K>(key[k], shift)] + rank[k];
+                        if (pos < (uint32_t)T) {
+                            s_keys[pos] = key[k];
+                            if constexpr (kHasVals) s_vals[pos] = val[k];
+                        } else {
+                            atomicOr(x.err, 4u);
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const uint32_t qq = k * THREADS + tid;
+                    if (qq < count) {
+                        const K kk = s_keys[qq];
+                        const uint32_t o = s_delta[digit_of<K>(kk, shift)] + qq;
+                        if (o < n) {
+                            to_global(dst_k)[o] = kk;
+                            if constexpr (kHasVals) to_global(dst_v)[o] = s_vals[qq];
+                        } else {
+                            atomicOr(x.err, 8u);
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // this pass's stores are visible to the workgroup's next pass
+            src_k = dst_k;
+            if constexpr (kHasVals) src_v = dst_v;
+            ++done;
         }
     }
 }
@@ -1022,7 +1229,7 @@ __global__ void k_seg_zero_hist(SegCtx x, int c) {
 
 // ---------------------------------------------------------------------------
 template <typename K, typename V>
-static hipError_t run_class(const SegCtx& x, int c, int persistent, int items, hipStream_t s) {
+static hipError_t run_class(const SegCtx& x, int c, int persistent, int threads, int items, hipStream_t s) {
     k_seg_zero_hist<<<1024, 256, 0, s>>>(x, c);
     k_seg_layout<<<1, 1024, 0, s>>>(x, c);
     k_seg_tilemap<<<256, 256, 0, s>>>(x, c);
@@ -1030,10 +1237,17 @@ static hipError_t run_class(const SegCtx& x, int c, int persistent, int items, h
     k_seg_scan<K><<<persistent, 256, 0, s>>>(x, c);
     k_seg_tiledesc<<<256, 256, 0, s>>>(x, c);
     for (int j = 0; j < (int)sizeof(K); ++j) {
-        if (items == 8) k_seg_scatter<K, V, 8><<<persistent, kSegTileThreads, 0, s>>>(x, c, j);
-        else k_seg_scatter<K, V, 16><<<persistent, kSegTileThreads, 0, s>>>(x, c, j);
+        if (threads == 256) {
+            if (items == 8) k_seg_scatter<K, V, 256, 8><<<persistent, 256, 0, s>>>(x, c, j);
+            else k_seg_scatter<K, V, 256, 16><<<persistent, 256, 0, s>>>(x, c, j);
+        } else {
+            if (items == 8) k_seg_scatter<K, V, 512, 8><<<persistent, 512, 0, s>>>(x, c, j);
+            else k_seg_scatter<K, V, 512, 16><<<persistent, 512, 0, s>>>(x, c, j);
+        }
     }
     k_seg_copy<K, V><<<persistent, 256, 0, s>>>(x, c);
+    if (items == 8) k_seg_wg<K, V, 8><<<persistent, 256, 0, s>>>(x, c);
+    else k_seg_wg<K, V, 16><<<persistent, 256, 0, s>>>(x, c);
     return hipGetLastError();
 }
 
@@ -1042,7 +1256,8 @@ uint32_t seg_max_tiles(uint64_t total_keys, uint32_t nseg) {
 }
 
 bool seg_tuning_valid(const fs_seg_tuning& t) {
-    return (t.tile_items == 8 || t.tile_items == 16) && t.large_wgs_per_cu >= 1 && t.large_wgs_per_cu <= 8 &&
+    return (t.tile_items == 8 || t.tile_items == 16) && (t.tile_threads == 256 || t.tile_threads == 512) &&
+           t.large_wgs_per_cu >= 1 && t.large_wgs_per_cu <= 8 &&
            t.small_wgs_per_cu >= 1 && t.small_wgs_per_cu <= 4 && t.expand16_wgs_per_cu >= 1 &&
            t.expand16_wgs_per_cu <= 2;
 }
@@ -1050,10 +1265,11 @@ bool seg_tuning_valid(const fs_seg_tuning& t) {
 hipError_t launch_segmented(const SegCtx& x0, const fs_seg_tuning& t, hipStream_t s) {
     const int cus = device_cu_count();
     SegCtx x = x0;
-    x.tile = (uint32_t)kSegTileThreads * t.tile_items;
+    x.tile = t.tile_threads * t.tile_items;
     for (int w = 0; w < 3; ++w) x.small_max[w] = t.small_max_keys[w] < kSegMinSmallMax ? kSegMinSmallMax : t.small_max_keys[w];
     x.expand_min = t.expand16_min_keys;
     x.split_min = t.expand16_split_keys < kX16MinSplit ? kX16MinSplit : t.expand16_split_keys;
+    x.wg_max = t.large_wg_max_keys;
     k_seg_classify<<<(x.nseg + 255) / 256 < 1024 ? (x.nseg + 255) / 256 : 1024, 256, 0, s>>>(x);
     const int xg = cus * (int)t.expand16_wgs_per_cu;
     k_seg_x16_layout<<<1, 1024, 0, s>>>(x);
@@ -1063,17 +1279,17 @@ hipError_t launch_segmented(const SegCtx& x0, const fs_seg_tuning& t, hipStream_
     k_seg_expand16<<<xg, kExpThreads, 0, s>>>(x);
     k_seg_small<<<cus * (int)t.small_wgs_per_cu, kSmallThreads, 0, s>>>(x);
     const int P = cus * (int)t.large_wgs_per_cu;
-    const int it = (int)t.tile_items;
+    const int it = (int)t.tile_items, th = (int)t.tile_threads;
     hipError_t e;
-    if ((e = run_class<uint16_t, NoVal>(x, 0, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint16_t, uint32_t>(x, 1, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint16_t, uint64_t>(x, 2, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, NoVal>(x, 3, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, uint32_t>(x, 4, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, uint64_t>(x, 5, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint64_t, NoVal>(x, 6, P, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint64_t, uint32_t>(x, 7, P, it, s)) != hipSuccess) return e;
-    return run_class<uint64_t, uint64_t>(x, 8, P, it, s);
+    if ((e = run_class<uint16_t, NoVal>(x, 0, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint16_t, uint32_t>(x, 1, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint16_t, uint64_t>(x, 2, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, NoVal>(x, 3, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, uint32_t>(x, 4, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, uint64_t>(x, 5, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint64_t, NoVal>(x, 6, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint64_t, uint32_t>(x, 7, P, th, it, s)) != hipSuccess) return e;
+    return run_class<uint64_t, uint64_t>(x, 8, P, th, it, s);
 }
 
 }  // namespace fs

@@ -574,7 +574,7 @@ void k_tile_scatter(TiledArgs a, int pass) {
             for (int k = 0; k < ITEMS; ++k) {
                 const bool valid = wbase + k * kWave + lane < count;
                 const K kk = kPack ? (K)kr[k] : key[kPack ? 0 : k];
-                const uint32_t r = wave_rank(digit_of<K>(kk, shift), valid, s_peers[wave], s_wcnt[wave]);
+                const uint32_t r = wave_rank_uniform_first(digit_of<K>(kk, shift), valid, s_peers[wave], s_wcnt[wave]);
                 if constexpr (kPack) kr[k] |= r << 16;
                 else kr[k] = r;
             }

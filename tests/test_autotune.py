@@ -14,8 +14,8 @@ LIB = os.path.join(ROOT, "paper_2605_10390_amd", "libfsort.so")
 FIELDS = [n for e in at.ORDER for n in (e if isinstance(e, tuple) else (e,))]
 
 START = {"small_max_keys": [at.NEVER, at.NEVER, at.NEVER], "expand16_min_keys": 8192,
-         "expand16_split_keys": 1 << 18, "expand16_wgs_per_cu": 1, "tile_items": 16,
-         "large_wgs_per_cu": 2, "small_wgs_per_cu": 2}
+         "expand16_split_keys": 1 << 18, "expand16_wgs_per_cu": 1, "large_wg_max_keys": 0, "tile_items": 16,
+         "tile_threads": 256, "large_wgs_per_cu": 2, "small_wgs_per_cu": 2}
 
 
 def separable_cost(target):
@@ -100,7 +100,8 @@ def test_library_accepts_every_candidate_and_rejects_out_of_range():
                 assert fs.get_tuning().as_dict() == t
         for name, v in (("tile_items", 12), ("tile_items", 32), ("large_wgs_per_cu", 0),
                         ("large_wgs_per_cu", 9), ("small_wgs_per_cu", 0), ("small_wgs_per_cu", 5),
-                        ("expand16_wgs_per_cu", 0), ("expand16_wgs_per_cu", 3)):
+                        ("expand16_wgs_per_cu", 0), ("expand16_wgs_per_cu", 3), ("tile_threads", 128),
+                        ("tile_threads", 1024)):
             before = fs.get_tuning().as_dict()
             with pytest.raises(fs.FsError):
                 fs.set_tuning(fs.SegTuning.from_dict(at.with_field(d, name, v)))

@@ -1,0 +1,38 @@
+"""Host-side accounting of bench.py (no GPU): which digits run, and the
+algorithmic bytes each pass and the whole sort must move."""
+import os
+import sys
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_active_digits():
+    k = torch.from_numpy(np.array([0x1200, 0x1234, 0x12FF], dtype=np.uint16))
+    assert bench.active_digits(k, 16) == [True, False]
+    k = torch.from_numpy(np.full(10, 0xABCD, dtype=np.uint16))
+    assert bench.active_digits(k, 16) == [False, False]
+    k = torch.from_numpy(np.array([1, 1 << 19, 5], dtype=np.uint32))
+    assert bench.active_digits(k, 32) == [True, False, True, False]
+    k = torch.from_numpy(np.array([0, 0xFF00000000000000], dtype=np.uint64))
+    assert bench.active_digits(k, 64) == [False] * 7 + [True]
+
+
+def test_pass_bytes():
+    # 16-bit pairs: the second pass stores only payloads
+    assert bench.scatter_pass_bytes(16, 4, [True, True]) == [12, 10]
+    assert bench.scatter_pass_bytes(16, 4, [False, True]) == [10]
+    assert bench.scatter_pass_bytes(16, 4, [True, False]) == [12]
+    assert bench.scatter_pass_bytes(32, 4, [True] * 4) == [16] * 4
+    assert bench.scatter_pass_bytes(64, 0, [True, False] * 4) == [16] * 4
+
+
+def test_whole_sort_bytes():
+    assert bench.algorithmic_bytes_per_key(16, 0, [True, True]) == 4
+    assert bench.algorithmic_bytes_per_key(16, 4, [True, True]) == 2 + 2 * 12
+    assert bench.algorithmic_bytes_per_key(32, 4, [True, True, False, False]) == 4 + 2 * 16
+    assert bench.algorithmic_bytes_per_key(64, 8, [False] * 8) == 8 + 2 * 16

@@ -155,13 +155,16 @@ NEVER = 0xFFFFFFFF
 TUNINGS = [
     None,  # process-wide default
     {"small_max_keys": [NEVER] * 3, "expand16_min_keys": NEVER, "expand16_split_keys": NEVER,
-     "expand16_wgs_per_cu": 1, "tile_items": 16, "large_wgs_per_cu": 2,
+     "expand16_wgs_per_cu": 1, "large_wg_max_keys": 0, "tile_items": 16, "tile_threads": 512,
+     "large_wgs_per_cu": 2,
      "small_wgs_per_cu": 2},  # 8-bit digits everywhere
     {"small_max_keys": [1024, 1024, 1024], "expand16_min_keys": 1, "expand16_split_keys": 1 << 18,
-     "expand16_wgs_per_cu": 2, "tile_items": 8, "large_wgs_per_cu": 8,
+     "expand16_wgs_per_cu": 2, "large_wg_max_keys": 1 << 16, "tile_items": 8, "tile_threads": 256,
+     "large_wgs_per_cu": 8,
      "small_wgs_per_cu": 1},  # every 16-bit keys-only segment expanded, long ones split
     {"small_max_keys": [4096, 2048, NEVER], "expand16_min_keys": 65536, "expand16_split_keys": NEVER,
-     "expand16_wgs_per_cu": 1, "tile_items": 8, "large_wgs_per_cu": 1,
+     "expand16_wgs_per_cu": 1, "large_wg_max_keys": 1 << 20, "tile_items": 8, "tile_threads": 512,
+     "large_wgs_per_cu": 1,
      "small_wgs_per_cu": 4},  # long ones on one workgroup each
 ]
 
