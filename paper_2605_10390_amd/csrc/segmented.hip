@@ -5,16 +5,20 @@
 // batch is a caller segment and every segment gets exactly the result a
 // stand-alone sort would give it.  Segment descriptors live in device
 // memory, so the whole schedule is decided on the device:
-//   1. classify: each segment goes to one of three bins by width and length
-//      (bounds from the launch tuning): the 16-bit-digit bin (16-bit keys
-//      without payload, long enough), the LDS bin (short enough to fit in
-//      one workgroup's LDS) or the large bin of its (key, value) class;
-//   2. 16-bit-digit bin: one workgroup per segment builds the compressed
-//      2^16-bin histogram in LDS and writes the sorted keys from it (one read
-//      and one write of HBM, no scatter);
+//   1. classify: each segment goes to one bin by width and length (bounds
+//      from the launch tuning, fs_seg_tuning): the 16-bit-digit bin (16-bit
+//      keys without payload, long enough), the LDS bin (short enough to fit
+//      in one workgroup's LDS), the one-workgroup bin or the large bin of its
+//      (key, value) class;
+//   2. 16-bit-digit bin: the segment's compressed 2^16-bin histogram is
+//      built in LDS and the sorted keys are written from it (one read and one
+//      write of HBM, no scatter); one workgroup per medium segment, 2^18-key
+//      parts of a long one on several;
 //   3. LDS bin: persistent workgroups pop the queue and sort each segment
 //      with 8-bit digits entirely in LDS (one read and one write of HBM);
-//   4. large segments, per width class: tile layout, per-segment digit
+//   4. one-workgroup bin, per width class: a workgroup sorts a whole segment
+//      with 8-bit digits through global memory, walking its tiles in order;
+//   5. large bin, per width class: tile layout, per-segment digit
 //      histograms (one read), per-segment prefix scans and pass plans, then
 //      one single-sweep scatter launch per digit over the tiles of all large
 //      segments of the class at once, with decoupled look-back confined to
@@ -41,7 +45,7 @@ constexpr uint32_t kSegAgg = 1u << kSegCountBits;
 constexpr uint32_t kSegPrefix = 2u << kSegCountBits;
 
 // counters (ctr[]): small count, small taken, per class: large count, tiles,
-// and one ticket per (class, pass)
+// one ticket per (class, pass); the 16-bit-digit and one-workgroup queues
 __host__ __device__ inline int ctr_large(int c) { return 2 + c; }
 __host__ __device__ inline int ctr_tiles(int c) { return 16 + c; }
 __host__ __device__ inline int ctr_ticket(int c, int j) { return 32 + 8 * c + j; }
