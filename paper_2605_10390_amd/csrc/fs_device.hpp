@@ -88,6 +88,32 @@ __device__ __forceinline__ void hist16_add(uint32_t* cnt, uint32_t key, uint32_t
     if (__builtin_expect(lo_wrap, 0)) atomicAdd(&wrap_lo[w], 1u);
 }
 
+// N compressed-histogram adds issued together: every returning LDS add is in
+// flight before any carry is examined, so a lane waits for LDS once per N
+// keys rather than once per key (a carry check between adds would order
+// them).  c[e] == 0 adds nothing and cannot carry; such an add goes to a
+// word picked by the lane (not the key's, which may be a hot one) so that it
+// costs no same-address conflict.  Each add still sees its own old word, so
+// every wrap is counted by exactly one add.  cnt holds 2^15 words.
+template <int N>
+__device__ __forceinline__ void hist16_add_n(uint32_t* cnt, const uint32_t* key, const uint32_t* c,
+                                             uint32_t* wrap_lo, uint32_t* wrap_word) {
+    uint32_t old[N], inc[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        inc[e] = (key[e] & 1u) ? (c[e] << 16) : c[e];
+        const uint32_t w = c[e] ? key[e] >> 1 : (threadIdx.x + 64u * e) & 0x7FFFu;
+        old[e] = atomicAdd(&cnt[w], inc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const bool word_wrap = (old[e] + inc[e]) < old[e];
+        const bool lo_wrap = ((old[e] & 0xFFFFu) + (inc[e] & 0xFFFFu)) > 0xFFFFu;
+        if (__builtin_expect(word_wrap, 0)) atomicAdd(&wrap_word[key[e] >> 1], 1u);
+        if (__builtin_expect(lo_wrap, 0)) atomicAdd(&wrap_lo[key[e] >> 1], 1u);
+    }
+}
+
 // Exclusive scan of one value per thread over the first 256 threads of a
 // block (4 waves); every thread of the block must call it.  `wsum` is LDS
 // scratch of at least 4 words.  Returns the exclusive prefix for threads

@@ -62,21 +62,20 @@ __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
                 hist16_add(cnt, kw, 8u * popc64(active), wrap_lo, wrap_word);
             continue;
         }
-        // otherwise one add per run of equal keys within the lane
-        uint32_t k[8];
+        // otherwise one add per run of equal keys within the lane (counted
+        // at the run's last key, 0 elsewhere), all issued together
+        uint32_t k[8], c[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) k[e] = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
         uint32_t run = 1;
 #pragma unroll
         for (int e = 0; e < 7; ++e) {
-            if (k[e + 1] == k[e]) {
-                ++run;
-            } else {
-                hist16_add(cnt, k[e], run, wrap_lo, wrap_word);
-                run = 1;
-            }
+            const bool same_next = k[e + 1] == k[e];
+            c[e] = same_next ? 0u : run;
+            run = same_next ? run + 1 : 1u;
         }
-        hist16_add(cnt, k[7], run, wrap_lo, wrap_word);
+        c[7] = run;
+        hist16_add_n<8>(cnt, k, c, wrap_lo, wrap_word);
     }
     // the few keys before the first 16-byte boundary and after the last vector
     if (blockIdx.x == 0) {

@@ -386,13 +386,32 @@ __device__ __forceinline__ void exp_hist(ExpandShared& sm, const uint16_t* keys,
         for (int u = 0; u < U; ++u) {
             const uint64_t i = i0 + (uint64_t)u * kExpThreads + tid;
             const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+            uint32_t w8[8], inc8[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const uint64_t idx = i * 8 + e;  // element index from a0; valid in [lead, lead + n)
-                if (idx < lead || idx >= lead + n) continue;
+                const bool valid = idx >= lead && idx < lead + n;
                 const uint32_t key = (wv[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-                if (may_carry) exp_add_logged(sm, key);
-                else atomicAdd(&sm.cnt[key >> 1], (key & 1u) ? 0x10000u : 1u);
+                // a masked key adds 0 to a word picked by the lane (no conflict)
+                w8[e] = valid ? key >> 1 : (threadIdx.x + 64u * e) & 0x7FFFu;
+                inc8[e] = valid ? ((key & 1u) ? 0x10000u : 1u) : 0u;
+            }
+            if (may_carry) {
+                // every returning add in flight before any carry is examined
+                uint32_t old[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) old[e] = atomicAdd(&sm.cnt[w8[e]], inc8[e]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const bool word_wrap = old[e] + inc8[e] < old[e];
+                    const bool lo_wrap = (old[e] & 0xFFFFu) + (inc8[e] & 0xFFFFu) > 0xFFFFu;
+                    if (__builtin_expect(word_wrap || lo_wrap, 0))
+                        exp_log(sm, w8[e], (uint32_t)lo_wrap, (uint32_t)word_wrap);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (inc8[e]) atomicAdd(&sm.cnt[w8[e]], inc8[e]);
             }
         }
     }

@@ -273,15 +273,24 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
                         atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
                     }
                 } else {
+                    // all adds issued before any carry check (hist16_add_n);
+                    // keys outside the range add 0
+                    uint32_t kk[VK], cc[VK];
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
                         const int32_t idx = first + e;
-                        if (idx >= 0 && idx < (int32_t)cntk) {
-                            const uint32_t key = k[e];
-                            hist16_add(cnt, key, 1u, wrap_lo, wrap_word);
-                            const uint32_t d = key & 0xFFu;
-                            atomicAdd(&s_t[par][(uint32_t)idx / TILE][copy][d >> 1], 1u << ((d & 1) * 16));
-                        }
+                        const bool in = idx >= 0 && idx < (int32_t)cntk;
+                        kk[e] = k[e];
+                        cc[e] = in ? 1u : 0u;
+                    }
+                    hist16_add_n<VK>(cnt, kk, cc, wrap_lo, wrap_word);
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const int32_t idx = first + e;
+                        const bool in = idx >= 0 && idx < (int32_t)cntk;
+                        const uint32_t d = kk[e] & 0xFFu;
+                        const uint32_t set = in ? (uint32_t)idx / TILE : 0u;
+                        atomicAdd(&s_t[par][set][copy][d >> 1], cc[e] << ((d & 1) * 16));
                     }
                 }
             }
