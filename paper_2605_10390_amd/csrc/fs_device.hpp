@@ -88,6 +88,27 @@ __device__ __forceinline__ void hist16_add(uint32_t* cnt, uint32_t key, uint32_t
     if (__builtin_expect(lo_wrap, 0)) atomicAdd(&wrap_lo[w], 1u);
 }
 
+// Leader aggregation of one add per lane: the lanes whose bucket id equals
+// that of the first active lane are summed into one add made by the lowest
+// of them (the others add nothing).  For skewed keys the first lane's bucket
+// is often a hot one, whose same-address adds would otherwise be serialised
+// by the LDS; for spread keys it matches only itself and nothing changes.
+// Lanes with in == false take no part.  Returns this lane's count; *shared
+// (wave-uniform) is how many lanes held the leader's bucket.
+__device__ __forceinline__ uint32_t leader_count(uint32_t id, bool in, uint32_t* shared) {
+    const uint32_t lead = __builtin_amdgcn_readfirstlane(in ? id : 0xFFFFFFFFu);
+    const uint64_t m = ballot(in && id == lead);
+    *shared = popc64(m);
+    if (!(m & (m - 1))) return in ? 1u : 0u;  // at most one lane holds the leader's bucket
+    if (in && id == lead) return lanes_below(m) == 0 ? popc64(m) : 0u;
+    return in ? 1u : 0u;
+}
+
+// Below this many lanes sharing the leader's bucket in a vector's first
+// element, a wave counts the vector's other elements one lane at a time:
+// spread keys then pay one leader check per vector, not one per key.
+constexpr uint32_t kSkewLanes = 4;
+
 // N compressed-histogram adds issued together: every returning LDS add is in
 // flight before any carry is examined, so a lane waits for LDS once per N
 // keys rather than once per key (a carry check between adds would order

@@ -305,36 +305,66 @@ __global__ __launch_bounds__(kSmallThreads) void k_seg_small(SegCtx x) {
 // ---------------------------------------------------------------------------
 constexpr int kExpThreads = 1024;
 constexpr int kExpGroups = 4096;    // 16-bin groups of the 2^16 bins
-constexpr int kExpEvents = 512;     // carry log (a segment below 2^23 keys logs fewer than 256)
+constexpr int kExpEvents = 256;     // carry log (a segment below 2^23 keys logs fewer than 256)
 
 struct ExpandShared {
     __attribute__((aligned(16))) uint32_t cnt[kHist16Words];  // bins 2w (low half) and 2w+1 (high half)
     uint32_t gpre[kExpGroups];            // exclusive prefix of every 16-bin group
     uint32_t carried[kHist16Words / 32];  // one bit per word that logged a carry
     uint32_t ev[kExpEvents];              // word | (1 << 31 for a carry out of the whole word)
+    uint32_t big_lo[kExpEvents];          // exact counts of the carried pairs (exp_settle);
+    uint32_t big_hi[kExpEvents];          //   such a pair's word then holds its index here
+    __attribute__((aligned(8))) uint16_t marks[kExpThreads / kWave][256];  // per-wave output marks
     uint32_t wsum[kExpThreads / kWave];
-    uint32_t nev;
+    uint32_t nev, nbig;
     uint32_t item, next;                  // queue entries: current and prefetched
 };
 
-// exact count of bin v
-__device__ __forceinline__ uint32_t exp_count(const ExpandShared& sm, uint32_t v, uint32_t nev) {
+// exact count of bin v (after exp_settle)
+__device__ __forceinline__ uint32_t exp_count(const ExpandShared& sm, uint32_t v) {
     const uint32_t w = v >> 1;
     const uint32_t word = sm.cnt[w];
     if (__builtin_expect(!((sm.carried[w >> 5] >> (w & 31)) & 1u), 1))
         return (v & 1u) ? (word >> 16) : (word & 0xFFFFu);
-    uint32_t nlo = 0, nword = 0;
-    for (uint32_t e = 0; e < nev; ++e) {
-        const uint32_t r = sm.ev[e];
-        if ((r & 0x7FFFFFFFu) == w) {
-            if (r >> 31) ++nword;
-            else ++nlo;
+    return (v & 1u) ? sm.big_hi[word] : sm.big_lo[word];
+}
+
+// Decode every carried pair once from the carry log into the exact-count
+// table and leave the table index in its word, so that a count is one
+// lookup however often it is read.  With W the word, nlo and nword the
+// pair's low-half and whole-word carries:
+//   lo = (W & 0xFFFF) + 2^16 nlo,  S = W + 2^32 nword = lo + 2^16 hi.
+// Every thread must call it, after the histogram is complete; a barrier
+// must follow.
+__device__ __forceinline__ void exp_settle(ExpandShared& sm, uint32_t* err) {
+    const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
+    if (threadIdx.x == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(err, 64u);
+    for (uint32_t cw = threadIdx.x; cw < (uint32_t)kHist16Words / 32; cw += kExpThreads) {
+        uint32_t bits = sm.carried[cw];
+        while (bits) {
+            const uint32_t w = 32 * cw + (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1;
+            uint32_t nlo = 0, nword = 0;
+            for (uint32_t e = 0; e < nev; ++e) {
+                const uint32_t r = sm.ev[e];
+                if ((r & 0x7FFFFFFFu) == w) {
+                    if (r >> 31) ++nword;
+                    else ++nlo;
+                }
+            }
+            const uint32_t word = sm.cnt[w];
+            const uint64_t lo = (uint64_t)(word & 0xFFFFu) + ((uint64_t)nlo << 16);
+            const uint64_t sum = (uint64_t)word + ((uint64_t)nword << 32);
+            const uint32_t k = atomicAdd(&sm.nbig, 1u);
+            if (k < (uint32_t)kExpEvents) {
+                sm.big_lo[k] = (uint32_t)lo;
+                sm.big_hi[k] = (uint32_t)((sum - lo) >> 16);
+                sm.cnt[w] = k;
+            } else {
+                atomicOr(err, 64u);
+            }
         }
     }
-    // sum of the increments S = lo + 2^16 * hi; the word holds S mod 2^32
-    const uint64_t lo = (uint64_t)(word & 0xFFFFu) + ((uint64_t)nlo << 16);
-    const uint64_t sum = (uint64_t)word + ((uint64_t)nword << 32);
-    return (v & 1u) ? (uint32_t)((sum - lo) >> 16) : (uint32_t)lo;
 }
 
 __device__ __forceinline__ void exp_log(ExpandShared& sm, uint32_t w, uint32_t nlo, uint32_t nword) {
@@ -361,7 +391,7 @@ __device__ __forceinline__ void exp_clear(ExpandShared& sm) {
     const u32x4 z = {0u, 0u, 0u, 0u};
     for (int i = tid; i < kHist16Words / 4; i += kExpThreads) c4[i] = z;
     for (int i = tid; i < kHist16Words / 32; i += kExpThreads) sm.carried[i] = 0;
-    if (tid == 0) sm.nev = 0;
+    if (tid == 0) sm.nev = sm.nbig = 0;
 }
 
 // histogram of keys [0, n) of `keys`: aligned 16-byte loads, keys outside
@@ -418,7 +448,7 @@ __device__ __forceinline__ void exp_hist(ExpandShared& sm, const uint16_t* keys,
 }
 
 // exclusive prefix of the 16-bin groups (thread t owns groups 4t..4t+3)
-__device__ __forceinline__ void exp_scan(ExpandShared& sm, uint32_t nev) {
+__device__ __forceinline__ void exp_scan(ExpandShared& sm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t gs[4], tot = 0;
 #pragma unroll
@@ -435,7 +465,7 @@ __device__ __forceinline__ void exp_scan(ExpandShared& sm, uint32_t nev) {
                        (q.z >> 16) + (q.w & 0xFFFFu) + (q.w >> 16);
             }
         } else {
-            for (int b = 0; b < 16; ++b) sum += exp_count(sm, 16u * g + b, nev);
+            for (int b = 0; b < 16; ++b) sum += exp_count(sm, 16u * g + b);
         }
         gs[k] = sum;
         tot += sum;
@@ -458,74 +488,154 @@ __device__ __forceinline__ void exp_scan(ExpandShared& sm, uint32_t nev) {
     }
 }
 
-// bin holding output position pos: the last group at or after g0 whose
-// prefix is <= pos, then its bins; start/end of the bin are returned
-__device__ __forceinline__ uint32_t exp_locate(const ExpandShared& sm, uint32_t pos, uint32_t g0,
-                                               uint32_t nev, uint32_t& end) {
-    uint32_t g = g0, len = (uint32_t)kExpGroups - g0;
-    while (len > 1) {
-        const uint32_t half = len >> 1;
-        if (sm.gpre[g + half] <= pos) g += half;
-        len -= half;
-    }
-    uint32_t v = 16u * g, start = sm.gpre[g], c = exp_count(sm, v, nev);
-    while (start + c <= pos && v < 0xFFFFu) {  // within the group (bounded even if counts were wrong)
-        start += c;
-        ++v;
-        c = exp_count(sm, v, nev);
-    }
-    end = start + c;
-    return v;
-}
-
-// write sorted positions [pa, pb) of the n-key output `out` from the LDS
-// histogram.  The output is cut into aligned 16-byte blocks (8 keys); block i
-// goes to this workgroup when its first in-range position lies in [pa, pb),
-// and lane i of the block loop writes block i, so a wave stores 1 KB of
-// contiguous output per instruction.
+// Write sorted positions [pa, pb) of the n-key output `out` from the LDS
+// histogram.  Every wave takes an equal share of the positions (skewed
+// histograms do not unbalance the waves) and finds the 16-bin group holding
+// its first position once, by binary search over the group prefixes.  It
+// then walks its share in chunks of 256 positions: one lane per group that
+// starts in the chunk walks that group's 16 bins and marks, in the wave's
+// LDS mark array, the chunk position where each non-empty bin starts (and
+// the bin holding the chunk's first position); a wave max-scan fills every
+// position with the last mark at or before it.  Every lane does the same
+// work, so no lane's walk holds the others up.  Lane i writes positions
+// 4i..4i+3 of the chunk with one aligned 8-byte store.
 __device__ __forceinline__ void exp_out(const ExpandShared& sm, uint16_t* out, uint64_t n, uint64_t pa,
-                                        uint64_t pb, uint32_t nev) {
-    const int tid = threadIdx.x;
-    const uintptr_t p = reinterpret_cast<uintptr_t>(out);
-    const uintptr_t a0 = p & ~(uintptr_t)15;
-    const uint64_t lead = (p - a0) >> 1;
-    // blocks whose first in-range position is in [pa, pb)
-    const uint64_t i_lo = pa == 0 ? 0 : (pa + lead + 7) >> 3;
-    const uint64_t i_hi = pb >= n ? (lead + n + 7) >> 3 : (pb + lead + 7) >> 3;
-    for (uint64_t i = i_lo + tid; i < i_hi; i += kExpThreads) {
-        const int64_t p0 = (int64_t)(i * 8) - (int64_t)lead;  // position of the block's first element
-        const uint32_t first = (uint32_t)(p0 < 0 ? 0 : p0);
-        uint32_t end;
-        uint32_t v = exp_locate(sm, first, 0, nev, end);
-        uint32_t o[8];
+                                        uint64_t pb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kExpThreads / kWave;
+    constexpr uint64_t kGroupCost = 8;  // a group walked costs about as much as 8 positions filled
+    uint16_t* const marks = const_cast<uint16_t*>(sm.marks[wave]);
+    // last group whose prefix is <= p, searched in [lo, kExpGroups)
+    auto group_of = [&](uint64_t p, uint32_t lo) {
+        uint32_t g = lo, len = (uint32_t)kExpGroups - lo;
+        while (len > 1) {
+            const uint32_t half = len >> 1;
+            if (sm.gpre[g + half] <= p) g += half;
+            len -= half;
+        }
+        return g;
+    };
+    // The wave's share of [pa, pb): cut points placed so that every wave
+    // gets the same positions + kGroupCost * groups (a sparse key range costs
+    // group walks, a dense one positions).  cost(g) is that measure at the
+    // start of group g; inside a group it grows by one per position, so a
+    // cut can fall inside a group and a hot group is shared by several waves.
+    const uint32_t ga = group_of(pa, 0), gz = group_of(pb - 1, ga) + 1;
+    auto pos_of = [&](uint32_t g) {
+        const uint64_t p = g < (uint32_t)kExpGroups ? sm.gpre[g] : n;
+        return p < pa ? pa : p > pb ? pb : p;
+    };
+    auto cost = [&](uint32_t g) { return pos_of(g) + kGroupCost * g; };
+    const uint64_t c_lo = cost(ga), c_span = cost(gz) - c_lo;
+    uint32_t g_w = ga;
+    auto cut = [&](int w, uint32_t* gw) -> uint64_t {  // position of the w-th cut, and its group
+        if (w == 0) {
+            *gw = ga;
+            return pa;
+        }
+        if (w == NW) {
+            *gw = gz;
+            return pb;
+        }
+        const uint64_t target = c_lo + c_span * (uint64_t)w / NW;
+        uint32_t g = ga, len = gz - ga + 1;
+        while (len > 1) {
+            const uint32_t half = len >> 1;
+            if (cost(g + half) <= target) g += half;
+            len -= half;
+        }
+        *gw = g;
+        const uint64_t p = pos_of(g) + (target - cost(g));
+        const uint64_t pe = g < gz ? pos_of(g + 1) : pb;
+        return p < pe ? p : pe;
+    };
+    uint32_t g_unused;
+    const uint64_t A = cut(wave, &g_w), B = cut(wave + 1, &g_unused);
+    if (A >= B) return;
+    uint32_t gc = g_w;  // at or before the group holding A
+    // 8-byte output quads: quad q holds positions 4q - lead .. 4q - lead + 3
+    const uint32_t lead = (uint32_t)((reinterpret_cast<uintptr_t>(out) & 7) >> 1);
+    for (uint64_t qc = (A + lead) >> 2;; qc += 64) {
+        const int64_t c0 = (int64_t)(4 * qc) - (int64_t)lead;  // chunk position of mark 0
+        if (c0 >= (int64_t)B) break;
+        const uint64_t f = c0 > (int64_t)A ? (uint64_t)c0 : A;  // first position written
+        const uint64_t cend = (uint64_t)(c0 + 256) < B ? (uint64_t)(c0 + 256) : B;
+        reinterpret_cast<uint64_t*>(marks)[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        // marks hold v - 16 gc (0 also for "no mark": the bin at f is the
+        // smallest, so filling from it is right either way)
+        const uint32_t vbase = 16u * gc;
+        uint32_t glast = gc;
+        for (uint32_t gb = gc;; gb += 64) {
+            // the group holding f, and every group that starts inside the
+            // chunk (not the empty groups whose prefix is the chunk's end)
+            const uint32_t g = gb + lane;
+            const bool act = g < (uint32_t)kExpGroups && (g == gc || sm.gpre[g] < cend);
+            if (act) {
+                uint32_t c[16];
+                const uint32_t w0 = 8 * g;
+                if ((sm.carried[w0 >> 5] >> (w0 & 31)) & 0xFFu) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t pos = p0 + e;
-            if (pos >= (int64_t)first && (uint64_t)pos < n && (uint32_t)pos >= end) {
-                // next bins: a short walk, else a search from the current group
-                int steps = 0;
-                while ((uint32_t)pos >= end && steps < 4 && v < 0xFFFFu) {
-                    ++v;
-                    end += exp_count(sm, v, nev);
-                    ++steps;
+                    for (int b = 0; b < 16; ++b) c[b] = exp_count(sm, 16 * g + b);
+                } else {
+                    const u32x4* c4 = reinterpret_cast<const u32x4*>(&sm.cnt[w0]);
+                    const u32x4 q0 = c4[0], q1 = c4[1];
+                    const uint32_t wd[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+                    for (int b = 0; b < 16; ++b) c[b] = (b & 1) ? wd[b >> 1] >> 16 : wd[b >> 1] & 0xFFFFu;
                 }
-                if ((uint32_t)pos >= end) v = exp_locate(sm, (uint32_t)pos, v >> 4, nev, end);
+                uint64_t st = sm.gpre[g];
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const uint32_t v = 16 * g + b;
+                    if (c[b]) {
+                        if (st >= f && st < cend)
+                            marks[st - c0] = (uint16_t)(v - vbase);  // a bin starting inside the chunk
+                        else if (st < f && f < st + c[b])
+                            marks[f - c0] = (uint16_t)(v - vbase);   // the bin holding the first position
+                    }
+                    st += c[b];
+                }
             }
-            o[e] = v;
+            const uint64_t am = ballot(act);
+            if (am) glast = gb + 63 - (uint32_t)__builtin_clzll(am);
+            if (am != ~0ull) break;  // group prefixes only grow: no later group starts in the chunk
         }
-        if (p0 >= 0 && (uint64_t)(p0 + 8) <= n) {
-            u32x4 q;
-            q.x = o[0] | (o[1] << 16);
-            q.y = o[2] | (o[3] << 16);
-            q.z = o[4] | (o[5] << 16);
-            q.w = o[6] | (o[7] << 16);
-            __builtin_nontemporal_store(q, (gptr<u32x4>)(a0 + 16 * i));
+        __builtin_amdgcn_wave_barrier();
+        // fill forward: inclusive max-scan over the 256 marks, 4 per lane
+        const uint64_t m4 = reinterpret_cast<const uint64_t*>(marks)[lane];
+        uint32_t r[4];
+        r[0] = (uint32_t)(m4 & 0xFFFFu);
+#pragma unroll
+        for (int e = 1; e < 4; ++e) {
+            const uint32_t me = (uint32_t)(m4 >> (16 * e)) & 0xFFFFu;
+            r[e] = me > r[e - 1] ? me : r[e - 1];
+        }
+        uint32_t inc = r[3];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off, 64);
+            if (lane >= off && y > inc) inc = y;
+        }
+        uint32_t before = __shfl_up(inc, 1, 64);
+        if (lane == 0) before = 0;
+        uint32_t key[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) key[e] = vbase + (r[e] > before ? r[e] : before);
+        const int64_t p0 = c0 + 4 * lane;
+        if (p0 >= (int64_t)f && (uint64_t)(p0 + 4) <= cend) {
+            const uint64_t qv = (uint64_t)key[0] | ((uint64_t)key[1] << 16) | ((uint64_t)key[2] << 32) |
+                                ((uint64_t)key[3] << 48);
+            __builtin_nontemporal_store(qv, (gptr<uint64_t>)(reinterpret_cast<uintptr_t>(out + p0)));
         } else {
-            for (int e = 0; e < 8; ++e) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
                 const int64_t pos = p0 + e;
-                if (pos >= 0 && (uint64_t)pos < n) to_global(out)[pos] = (uint16_t)o[e];
+                if (pos >= (int64_t)f && (uint64_t)pos < cend) to_global(out)[pos] = (uint16_t)key[e];
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        gc = glast;  // at or before the group holding the next chunk's first position
     }
 }
 
@@ -551,11 +661,11 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_expand16(SegCtx x) {
         __syncthreads();
         exp_hist(sm, static_cast<const uint16_t*>(d.keys_in), d.n);
         __syncthreads();
-        const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
-        if (tid == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(x.err, 64u);
-        exp_scan(sm, nev);
+        exp_settle(sm, x.err);
         __syncthreads();
-        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, 0, d.n, nev);
+        exp_scan(sm);
+        __syncthreads();
+        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, 0, d.n);
     }
 }
 
@@ -627,15 +737,15 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_x16_hist(SegCtx x) {
         __syncthreads();
         exp_hist(sm, static_cast<const uint16_t*>(d.keys_in) + b0, m);
         __syncthreads();
-        const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
-        if (tid == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(x.err, 64u);
+        exp_settle(sm, x.err);
+        __syncthreads();
         // add the exact nonzero counts to the segment's histogram
         uint32_t* gh = x.x16_hist + (uint64_t)q * 65536;
         for (uint32_t w = tid; w < (uint32_t)kHist16Words; w += kExpThreads) {
             const uint32_t word = sm.cnt[w];
             const bool carried = (sm.carried[w >> 5] >> (w & 31)) & 1u;
-            const uint32_t lo = carried ? exp_count(sm, 2 * w, nev) : word & 0xFFFFu;
-            const uint32_t hi = carried ? exp_count(sm, 2 * w + 1, nev) : word >> 16;
+            const uint32_t lo = carried ? exp_count(sm, 2 * w) : word & 0xFFFFu;
+            const uint32_t hi = carried ? exp_count(sm, 2 * w + 1) : word >> 16;
             if (lo) atomicAdd(&gh[2 * w], lo);
             if (hi) atomicAdd(&gh[2 * w + 1], hi);
         }
@@ -654,25 +764,31 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_x16_out(SegCtx x) {
         const uint64_t pa = (uint64_t)(part - x.x16_parts[q]) * kX16Part;
         const uint64_t pb = d.n - pa < kX16Part ? d.n : pa + kX16Part;
         // the segment's exact counts back into the packed LDS form; a pair
-        // whose low count or whole sum overflows is represented by carry
-        // events that decode to the exact counts
+        // with a count past 65535 goes to the exact-count table
         if (tid < kHist16Words / 32) sm.carried[tid] = 0;
-        if (tid == 0) sm.nev = 0;
+        if (tid == 0) sm.nbig = 0;
         __syncthreads();
         const uint32_t* gh = x.x16_hist + (uint64_t)q * 65536;
         for (uint32_t w = tid; w < (uint32_t)kHist16Words; w += kExpThreads) {
             const uint32_t lo = gh[2 * w], hi = gh[2 * w + 1];
-            const uint64_t sum = (uint64_t)lo + ((uint64_t)hi << 16);
-            sm.cnt[w] = (uint32_t)sum;
-            if (__builtin_expect(lo > 0xFFFFu || (sum >> 32) != 0, 0))
-                exp_log(sm, w, lo >> 16, (uint32_t)(sum >> 32));
+            if (__builtin_expect((lo | hi) > 0xFFFFu, 0)) {
+                const uint32_t k = atomicAdd(&sm.nbig, 1u);
+                if (k < (uint32_t)kExpEvents) {
+                    sm.big_lo[k] = lo;
+                    sm.big_hi[k] = hi;
+                    sm.cnt[w] = k;
+                    atomicOr(&sm.carried[w >> 5], 1u << (w & 31));
+                } else {
+                    atomicOr(x.err, 64u);
+                }
+            } else {
+                sm.cnt[w] = lo | (hi << 16);
+            }
         }
         __syncthreads();
-        const uint32_t nev = sm.nev < (uint32_t)kExpEvents ? sm.nev : (uint32_t)kExpEvents;
-        if (tid == 0 && sm.nev > (uint32_t)kExpEvents) atomicOr(x.err, 64u);
-        exp_scan(sm, nev);
+        exp_scan(sm);
         __syncthreads();
-        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, pa, pb, nev);
+        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, pa, pb);
         __syncthreads();
     }
 }
@@ -751,6 +867,7 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_hist(SegCtx x, int c) {
     const uint32_t per = (tiles + gridDim.x - 1) / gridDim.x;
     const uint32_t g0 = blockIdx.x * per, g1 = g0 + per < tiles ? g0 + per : tiles;
     for (int i = tid; i < D * kRadix; i += kSegTileThreads) (&cnt[0][0])[i] = 0;
+    __syncthreads();  // every counter is zero before any wave counts into it
     for (uint32_t g = g0; g < g1;) {
         const uint32_t q = x.tile_seg[g];
         const uint32_t tq0 = x.tile_prefix[q], tq1 = x.tile_prefix[q + 1];

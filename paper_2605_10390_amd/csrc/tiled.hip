@@ -141,12 +141,23 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
                         }
                     }
                 } else {
+                    bool skewed = false;
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
                         const int32_t idx = first + e;
-                        if (idx >= 0 && idx < (int32_t)cnt) {
-                            const uint32_t d = digit_of<K>(k[e], shift);
-                            atomicAdd(&s_t[par][(uint32_t)idx / TILE][copy][d >> 1], 1u << ((d & 1) * 16));
+                        const bool in = idx >= 0 && idx < (int32_t)cnt;
+                        const uint32_t d = digit_of<K>(k[e], shift);
+                        const uint32_t set = in ? (uint32_t)idx / TILE : 0u;
+                        // lanes sharing the leader's (tile, digit) add once
+                        // (checked on the first element, kept if it paid)
+                        uint32_t c = in ? 1u : 0u;
+                        if (e == 0 || skewed) {
+                            uint32_t sh;
+                            c = leader_count((set << 8) | d, in, &sh);
+                            if (e == 0) skewed = sh >= kSkewLanes;
+                        }
+                        if (c) atomicAdd(&s_t[par][set][copy][d >> 1], c << ((d & 1) * 16));
+                        if (in) {
                             if constexpr (FIRST) {
 #pragma unroll
                                 for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
@@ -275,22 +286,28 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
                 } else {
                     // all adds issued before any carry check (hist16_add_n);
                     // keys outside the range add 0
-                    uint32_t kk[VK], cc[VK];
+                    // lanes sharing the leader's (tile, key) add once (checked
+                    // on the first element, kept if it paid)
+                    uint32_t kk[VK], cc[VK], st[VK];
+                    bool skewed = false;
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
                         const int32_t idx = first + e;
                         const bool in = idx >= 0 && idx < (int32_t)cntk;
                         kk[e] = k[e];
+                        st[e] = in ? (uint32_t)idx / TILE : 0u;
                         cc[e] = in ? 1u : 0u;
+                        if (e == 0 || skewed) {
+                            uint32_t sh;
+                            cc[e] = leader_count((st[e] << 16) | kk[e], in, &sh);
+                            if (e == 0) skewed = sh >= kSkewLanes;
+                        }
                     }
                     hist16_add_n<VK>(cnt, kk, cc, wrap_lo, wrap_word);
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
-                        const int32_t idx = first + e;
-                        const bool in = idx >= 0 && idx < (int32_t)cntk;
                         const uint32_t d = kk[e] & 0xFFu;
-                        const uint32_t set = in ? (uint32_t)idx / TILE : 0u;
-                        atomicAdd(&s_t[par][set][copy][d >> 1], cc[e] << ((d & 1) * 16));
+                        if (cc[e]) atomicAdd(&s_t[par][st[e]][copy][d >> 1], cc[e] << ((d & 1) * 16));
                     }
                 }
             }

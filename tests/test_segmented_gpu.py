@@ -245,3 +245,26 @@ def test_autotuner_picks_a_valid_tuning(gpu):
     torch.cuda.synchronize()
     assert ws.error_word() == 0
     check(host, devs)
+
+
+def test_large_bin_histograms_start_from_zero(gpu):
+    """Regression: the large-bin digit histograms must be cleared before any
+    wave counts into them.  Many 16-bit keys-only segments through the large
+    bin with eight workgroups per CU (short per-workgroup stretches, where a
+    missing barrier after the clear lost counts), repeated."""
+    host, devs = [], []
+    for i in range(24):
+        h, d = make_segment(150000 + 4099 * i, 16, 0, ("uniform", "zipf")[i % 2], fsgen.seed_for(9, i), gpu)
+        host.append(h)
+        devs.append(d)
+    t = fs.SegTuning.from_dict({"small_max_keys": [NEVER] * 3, "expand16_min_keys": NEVER,
+                                "expand16_split_keys": NEVER, "expand16_wgs_per_cu": 1,
+                                "large_wg_max_keys": 0, "tile_items": 8, "tile_threads": 256,
+                                "large_wgs_per_cu": 8, "small_wgs_per_cu": 2})
+    batch = fs.SegmentBatch(devs)
+    ws = fs.Workspace(gpu)
+    for _ in range(6):
+        batch.run(ws, tuning=t)
+        torch.cuda.synchronize()
+        assert ws.error_word() == 0
+        check(host, devs)
