@@ -189,21 +189,30 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint64_t* 
     return before + below;
 }
 
-// wave_rank with a fast path for a wave whose valid lanes all hold the same
-// digit (presorted, reverse-sorted or hot-key input): the rank is then the
-// lane's position among the valid lanes, and the LDS word every lane would
-// OR into (a 64-way same-address conflict) is not touched.
+// wave_rank with a fast path for the digit of the wave's first valid lane:
+// the lanes holding it are ranked by their position among themselves, so
+// they never touch the LDS word every one of them would OR into (a
+// same-address conflict as wide as the group).  When that digit is every
+// valid lane's (presorted, reverse-sorted, hot-key input) nothing else is
+// done; when it is shared by at least kRankLeaderLanes lanes (skewed keys)
+// the other lanes are ranked by wave_rank, which reads and updates other
+// digits' counts only.
+constexpr uint32_t kRankLeaderLanes = 8;
 __device__ __forceinline__ uint32_t wave_rank_uniform_first(uint32_t d, bool valid, uint64_t* peers_w,
                                                             uint32_t* cnt_w) {
     const uint64_t vm = ballot(valid);
     const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xFFFFFFFFu);
-    if (vm != 0 && ballot(valid && d == d0) == vm) {
+    const uint64_t m = ballot(valid && d == d0);
+    if (vm != 0 && (m == vm || popc64(m) >= kRankLeaderLanes)) {
+        const bool mine = valid && d == d0;
         const uint32_t before = cnt_w[d0];
-        const uint32_t below = lanes_below(vm);
+        const uint32_t below = lanes_below(m);
         __builtin_amdgcn_wave_barrier();
-        if (valid && below == 0) cnt_w[d0] = before + popc64(vm);
+        if (mine && below == 0) cnt_w[d0] = before + popc64(m);
         __builtin_amdgcn_wave_barrier();
-        return before + below;
+        if (m == vm) return before + below;
+        const uint32_t r = wave_rank(d, valid && !mine, peers_w, cnt_w);
+        return mine ? before + below : r;
     }
     return wave_rank(d, valid, peers_w, cnt_w);
 }

@@ -109,6 +109,19 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
             const uint32_t v = tid + r * kTileHistThreads;
             if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
         }
+        // skewed digits: is the digit of the wave's first key shared by at
+        // least kSkewLanes lanes in the step's first vector?  (wave-uniform;
+        // spread keys then count exactly as without the check)
+        bool skewed = false;
+        {
+            const uint32_t v = tid;
+            const bool in0 = v < nv && (int32_t)(v * VK) - (int32_t)sh >= 0;
+            K k0[VK];
+            __builtin_memcpy(k0, &q[0], 16);
+            const uint32_t d0 = digit_of<K>(k0[0], shift);
+            const uint32_t lead = __builtin_amdgcn_readfirstlane(in0 ? d0 : 0xFFFFFFFFu);
+            skewed = popc64(ballot(in0 && d0 == lead)) >= kSkewLanes;
+        }
 #pragma unroll
         for (int r = 0; r <= kHistVecs; ++r) {
             const uint32_t v = tid + r * kTileHistThreads;
@@ -140,24 +153,31 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
                             for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<uint64_t>(kw, 8 * j)], c);
                         }
                     }
-                } else {
-                    bool skewed = false;
+                } else if (skewed) {
+                    // lanes sharing the leader's (tile, digit) add once
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
                         const int32_t idx = first + e;
                         const bool in = idx >= 0 && idx < (int32_t)cnt;
                         const uint32_t d = digit_of<K>(k[e], shift);
                         const uint32_t set = in ? (uint32_t)idx / TILE : 0u;
-                        // lanes sharing the leader's (tile, digit) add once
-                        // (checked on the first element, kept if it paid)
-                        uint32_t c = in ? 1u : 0u;
-                        if (e == 0 || skewed) {
-                            uint32_t sh;
-                            c = leader_count((set << 8) | d, in, &sh);
-                            if (e == 0) skewed = sh >= kSkewLanes;
-                        }
+                        uint32_t shared;
+                        const uint32_t c = leader_count((set << 8) | d, in, &shared);
                         if (c) atomicAdd(&s_t[par][set][copy][d >> 1], c << ((d & 1) * 16));
                         if (in) {
+                            if constexpr (FIRST) {
+#pragma unroll
+                                for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
+                            }
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const int32_t idx = first + e;
+                        if (idx >= 0 && idx < (int32_t)cnt) {
+                            const uint32_t d = digit_of<K>(k[e], shift);
+                            atomicAdd(&s_t[par][(uint32_t)idx / TILE][copy][d >> 1], 1u << ((d & 1) * 16));
                             if constexpr (FIRST) {
 #pragma unroll
                                 for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
