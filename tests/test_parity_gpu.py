@@ -174,3 +174,39 @@ def test_many_offset_levels_and_ragged_tail(gpu):
     ek, ev = oracle.sort(k, np.arange(n, dtype=np.uint32))
     assert np.array_equal(host(ko), ek)
     assert np.array_equal(host(vo), ev)
+
+
+def test_pair_sorts_with_one_active_digit_and_in_a_graph(gpu):
+    """16-bit pair sorts above 2^22 keys, whose keys are expanded from the
+    2^16-bin prefix: only the second digit active (the low byte is
+    constant), only the first (the high byte is constant; that pass is then
+    the last and writes the keys too, the same values the expansion
+    writes), both; and the same sort captured into a hipGraph, replayed
+    twice with the outputs cleared in between."""
+    n = (1 << 22) + 3
+    rng = np.random.default_rng(5)
+    idx = np.arange(n, dtype=np.uint32)
+    cases = [(rng.integers(0, 256, n) << 8).astype(np.uint16),        # digit 0 trivial
+             (0x3A00 | rng.integers(0, 256, n)).astype(np.uint16),    # digit 1 trivial
+             rng.integers(0, 65536, n).astype(np.uint16)]
+    for keys in cases:
+        ko, vo = fs.sort_pairs(dev(keys), dev(idx))
+        torch.cuda.synchronize()
+        ek, ev = oracle.sort(keys, idx)
+        assert np.array_equal(host(ko), ek)
+        assert np.array_equal(host(vo), ev)
+    keys = cases[2]
+    kd, vd = dev(keys), dev(idx)
+    ko, vo = torch.empty_like(kd), torch.empty_like(vd)
+    ws = fs.Workspace(gpu)
+    ws.get(fs.sort_pairs_workspace_bytes(n, 16, 4))
+    g = fs.CapturedSort(lambda: fs.sort_pairs(kd, vd, keys_out=ko, vals_out=vo, workspace=ws), gpu)
+    ek, ev = oracle.sort(keys, idx)
+    for _ in range(2):
+        ko.view(torch.int16).zero_()
+        vo.view(torch.int32).zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ko), ek)
+        assert np.array_equal(host(vo), ev)
