@@ -111,8 +111,10 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         }
         // skewed digits: is the digit of the wave's first key shared by at
         // least kSkewLanes lanes in the step's first vector?  (wave-uniform;
-        // spread keys then count exactly as without the check)
+        // spread keys then count exactly as without the check.)  Bit j of
+        // skew_all answers it for digit j of the first pass's totals.
         bool skewed = false;
+        uint32_t skew_all = 0;
         {
             const uint32_t v = tid;
             const bool in0 = v < nv && (int32_t)(v * VK) - (int32_t)sh >= 0;
@@ -121,7 +123,32 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
             const uint32_t d0 = digit_of<K>(k0[0], shift);
             const uint32_t lead = __builtin_amdgcn_readfirstlane(in0 ? d0 : 0xFFFFFFFFu);
             skewed = popc64(ballot(in0 && d0 == lead)) >= kSkewLanes;
+            if constexpr (FIRST) {
+#pragma unroll
+                for (int j = 1; j < D; ++j) {
+                    const uint32_t dj = digit_of<K>(k0[0], 8 * j);
+                    const uint32_t lj = __builtin_amdgcn_readfirstlane(in0 ? dj : 0xFFFFFFFFu);
+                    if (popc64(ballot(in0 && dj == lj)) >= kSkewLanes) skew_all |= 1u << j;
+                }
+            }
         }
+        // the first pass's totals of digit j for one element (leader
+        // aggregation when that digit is skewed in this step)
+        auto count_all = [&](const K key, bool in) {
+            if constexpr (FIRST) {
+#pragma unroll
+                for (int j = 1; j < D; ++j) {
+                    const uint32_t dj = digit_of<K>(key, 8 * j);
+                    if ((skew_all >> j) & 1u) {
+                        uint32_t shared;
+                        const uint32_t c = leader_count(dj, in, &shared);
+                        if (c) atomicAdd(&s_all[j][dj], c);
+                    } else if (in) {
+                        atomicAdd(&s_all[j][dj], 1u);
+                    }
+                }
+            }
+        };
 #pragma unroll
         for (int r = 0; r <= kHistVecs; ++r) {
             const uint32_t v = tid + r * kTileHistThreads;
@@ -164,21 +191,20 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
                         uint32_t shared;
                         const uint32_t c = leader_count((set << 8) | d, in, &shared);
                         if (c) atomicAdd(&s_t[par][set][copy][d >> 1], c << ((d & 1) * 16));
-                        if (in) {
-                            if constexpr (FIRST) {
-#pragma unroll
-                                for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
-                            }
-                        }
+                        count_all(k[e], in);
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
                         const int32_t idx = first + e;
-                        if (idx >= 0 && idx < (int32_t)cnt) {
+                        const bool in = idx >= 0 && idx < (int32_t)cnt;
+                        if (in) {
                             const uint32_t d = digit_of<K>(k[e], shift);
                             atomicAdd(&s_t[par][(uint32_t)idx / TILE][copy][d >> 1], 1u << ((d & 1) * 16));
-                            if constexpr (FIRST) {
+                        }
+                        if constexpr (FIRST) {
+                            if (skew_all) count_all(k[e], in);
+                            else if (in) {
 #pragma unroll
                                 for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<K>(k[e], 8 * j)], 1u);
                             }
