@@ -316,6 +316,75 @@ def run_c4(args):
     print(json.dumps(out), flush=True)
 
 
+PCIE5_X16_GBPS = 63.0  # per direction: 32 GT/s x 16 lanes, 128b/130b coding
+
+
+def run_stream16(args):
+    """Batch stream sorting of 16-bit keys that live in host memory: 2^31
+    uint16 keys (4 GiB, pinned), copied to the device 2^26 keys at a time,
+    counted into one resident 2^16-bin histogram as they arrive and written
+    back sorted through the same staging slots (fs_sort16_host).  The host
+    link carries 2 B per key in and 2 B out, one direction after the other,
+    so the bound is the link's per-direction rate; the plain pinned copy
+    rates of both directions are measured beside it."""
+    import torch
+    import fsgen
+    import paper_2605_10390_amd as fs
+    dev = torch.device("cuda:0")
+    n, batch = 1 << 31, 1 << 26
+    seed = fsgen.seed_for(1, 0)
+    src = torch.empty(n, dtype=torch.uint16, pin_memory=True)
+    src.copy_(fsgen.keys_device("uniform", 16, n, seed, device=dev))
+    out = torch.empty(n, dtype=torch.uint16, pin_memory=True)
+    ws = fs.Workspace(dev)
+    ws.get(fs.sort16_host_workspace_bytes(batch))
+    xs = torch.cuda.Stream(dev)
+    # plain pinned copies of the same 4 GiB, each direction alone
+    d = torch.empty(n, dtype=torch.uint16, device=dev)
+    rates = {}
+    for name, (dst, srct) in (("h2d", (d, src)), ("d2h", (out, d))):
+        dst.copy_(srct, non_blocking=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(srct, non_blocking=True)
+        torch.cuda.synchronize()
+        rates[name] = 2 * n / (time.perf_counter() - t0) / 1e9
+    del d
+    for _ in range(args.warmup):
+        fs.sort16_host(src, out=out, batch_keys=batch, workspace=ws, copy_stream=xs, device=dev)
+    print(f"[bench] stream16 warmup done; pinned copy GB/s {rates}", file=sys.stderr, flush=True)
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fs.sort16_host(src, out=out, batch_keys=batch, workspace=ws, copy_stream=xs, device=dev)
+        times.append(time.perf_counter() - t0)  # the call returns with the host output complete
+    ms = 1e3 * sum(times) / len(times)
+    o = out.view(torch.int16)
+    step = 1 << 28
+    for a in range(0, n, step):  # cheap validity check outside the timed region
+        c = o[a:a + step].to(torch.int32) & 0xFFFF
+        assert bool((c[1:] >= c[:-1]).all()), "output not sorted"
+    achieved = 4 * n / (ms / 1e3) / 1e9
+    ideal_ms = 1e3 * (2 * n / (rates["h2d"] * 1e9) + 2 * n / (rates["d2h"] * 1e9))
+    res = {"metric": "Gkeys/s, 16-bit keys sorted host to host through the device (batch stream)",
+           "value": round(n / (ms / 1e3) / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+           "config": {"workload": "batch stream sort of 2^31 uint16 keys (4 GiB) in pinned host memory, "
+                                  "2^26-key batches, uniform", "n": n, "batch_keys": batch, "seed": seed,
+                      "parallelism": "single GPU, copy stream + compute stream"},
+           "roofline": {"bound": "pcie", "kernel": None, "achieved": round(achieved, 2),
+                        "peak": PCIE5_X16_GBPS, "unit": "GB/s", "frac": round(achieved / PCIE5_X16_GBPS, 4),
+                        "traffic": None, "bytes_per_key": 4},
+           "pinned_copy_gbps": {k: round(v, 2) for k, v in rates.items()},
+           "frac_of_measured_copies": round(ideal_ms / ms, 4)}
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(src, None, 16, 0)
+    print(json.dumps(res), flush=True)
+
+
 def pmc_summary(fetch_csv, write_csv, kernel, out_path, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
     dispatch) of `bench.py --copy-probe` into HBM bytes per launch of
@@ -353,7 +422,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4"])
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4", "stream16"])
     ap.add_argument("--jobs", type=int, default=1000, help="served-stream prefix length (c4)")
     ap.add_argument("--dist", default=None,
                     help="c0/c1/c2a/c2b: key distribution (16-bit: uniform gaussian zipf equal presorted "
@@ -381,6 +450,8 @@ def main():
         return run_c3(args)
     if args.workload == "c4":
         return run_c4(args)
+    if args.workload == "stream16":
+        return run_stream16(args)
 
     import torch
     import ctypes

@@ -197,6 +197,62 @@ fs_status fs_sort_segmented_tuned(const fs_segment *d_segments, uint32_t num_seg
                                   size_t *workspace_bytes, void *stream);
 
 /* Human-readable name of a status code (static storage). */
+/*
+ * Batch stream sorting of 16-bit keys (Section I, contribution 2; batches,
+ * Section III-C; reconstruction from the counters, Algorithm 5 with no
+ * trailing bits).  For 16-bit keys the 2^16-bin histogram is the whole
+ * multiset, so batches that arrive one after another are sorted by adding
+ * each one's histogram into a resident histogram and writing the sorted
+ * keys from it once the stream ends; no batch has to stay resident.
+ *
+ * fs_hist16_accumulate: d_hist[v] += #{ i < n : keys[i] == v } for all
+ *   v < 2^16.  keys: device, n 16-bit keys.  d_hist: device, 65536 uint64,
+ *   8-byte aligned, caller-initialised (zero it before the first batch);
+ *   must not overlap keys or the workspace.  Workspace as for every call
+ *   (its size depends on n only).  n == 0 adds nothing.
+ */
+fs_status fs_hist16_accumulate(const void *keys, uint64_t n, uint64_t *d_hist, void *workspace,
+                               size_t *workspace_bytes, void *stream);
+
+/*
+ * fs_hist16_prefix: exclusive prefix of a 2^16-bin histogram (GetIndex of
+ *   every value, Algorithm 3): d_prefix[v] = sum of d_hist[u] for u < v,
+ *   v = 0..65536, so d_prefix[65536] is the number of keys.  Both device,
+ *   8-byte aligned, not overlapping (65536 and 65537 uint64).
+ */
+fs_status fs_hist16_prefix(const uint64_t *d_hist, uint64_t *d_prefix, void *stream);
+
+/*
+ * fs_expand16: positions [first, first + count) of the sorted multiset that
+ *   d_prefix (from fs_hist16_prefix) describes: keys_out[i - first] = v for
+ *   d_prefix[v] <= i < d_prefix[v + 1].  keys_out: device, count 16-bit
+ *   keys, not overlapping d_prefix.  Positions at or beyond the total
+ *   d_prefix[65536] are left unwritten.  Any range may be asked for, in any
+ *   order, so the output can be produced in pieces.
+ */
+fs_status fs_expand16(const uint64_t *d_prefix, uint64_t first, uint64_t count, void *keys_out,
+                      void *stream);
+
+/*
+ * fs_sort16_host: ascending sort of n 16-bit keys that live in HOST memory
+ *   (the input need not fit in device memory).  The keys are copied in
+ *   batch_keys at a time through two device staging slots in the workspace
+ *   and counted with fs_hist16_accumulate as they arrive; the sorted keys
+ *   are then written back to h_keys_out through the same slots.
+ *   h_keys_in / h_keys_out: host, n 16-bit keys; they may be the same
+ *   buffer (in-place) but must not otherwise overlap.  Pinned host memory
+ *   (hipHostMalloc) lets copies and counting overlap; pageable memory works
+ *   at the copy speed of the runtime's staging.
+ *   copy_stream / compute_stream: hipStream_t's for the copies and the
+ *   kernels (they may be the same stream; NULL = the default stream).
+ *   The workspace size depends on batch_keys only.  Unlike the other calls
+ *   this one BLOCKS until h_keys_out holds the result (both streams are
+ *   synchronised).  n == 0 is FS_OK and a no-op.
+ */
+fs_status fs_sort16_host(const void *h_keys_in, void *h_keys_out, uint64_t n, uint64_t batch_keys,
+                         void *workspace, size_t *workspace_bytes, void *copy_stream,
+                         void *compute_stream);
+
 const char *fs_status_string(fs_status s);
 
 #ifdef __cplusplus

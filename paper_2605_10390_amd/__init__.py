@@ -63,6 +63,14 @@ def lib():
     L.fs_profile_read.argtypes = [i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
                                   ctypes.POINTER(ctypes.c_double)]
     L.fs_profile_read.restype = i32
+    L.fs_hist16_accumulate.argtypes = [vp, u64, vp, vp, sz, vp]
+    L.fs_hist16_accumulate.restype = i32
+    L.fs_hist16_prefix.argtypes = [vp, vp, vp]
+    L.fs_hist16_prefix.restype = i32
+    L.fs_expand16.argtypes = [vp, u64, u64, vp, vp]
+    L.fs_expand16.restype = i32
+    L.fs_sort16_host.argtypes = [vp, vp, u64, u64, vp, sz, vp, vp]
+    L.fs_sort16_host.restype = i32
     L.fs_status_string.argtypes = [i32]
     L.fs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -361,3 +369,97 @@ def sort_segmented(segments, workspace=None, tuning=None):
     """Sort every (keys_in, keys_out, vals_in, vals_out) segment independently
     in one call; returns the workspace (its error word is 0 on success)."""
     return SegmentBatch(segments).run(workspace, tuning=tuning)
+
+
+# ------------------------------------------------------- batch stream sorting
+# 16-bit keys: the 2^16-bin histogram is the whole multiset, so a stream of
+# batches is sorted by accumulating their histograms and expanding the sum.
+
+def _u16(t, what):
+    if t.dtype not in (torch.uint16, torch.int16):
+        raise TypeError(f"{what} must hold 16-bit keys, not {t.dtype}")
+
+
+def new_hist16(device="cuda"):
+    """A zeroed resident 2^16-bin histogram (int64 tensor holding uint64 counts)."""
+    return torch.zeros(65536, dtype=torch.int64, device=device)
+
+
+def hist16_accumulate(keys, hist, workspace=None):
+    """hist[v] += number of keys equal to v (keys: 1-D 16-bit device tensor)."""
+    _check_dev(keys, hist)
+    _u16(keys, "keys")
+    if hist.dtype != torch.int64 or hist.numel() != 65536:
+        raise ValueError("hist must be an int64 tensor of 65536 counts")
+    n = keys.numel()
+    L = lib()
+    size = ctypes.c_size_t(0)
+    st = L.fs_hist16_accumulate(None, n, None, None, ctypes.byref(size), None)
+    if st != FS_OK:
+        raise FsError(st, "fs_hist16_accumulate (workspace query)")
+    ws = workspace or Workspace(keys.device)
+    buf = ws.get(size.value)
+    size = ctypes.c_size_t(buf.numel())
+    st = L.fs_hist16_accumulate(_ptr(keys), n, _ptr(hist), _ptr(buf), ctypes.byref(size), _stream(keys))
+    if st != FS_OK:
+        raise FsError(st, "fs_hist16_accumulate")
+    return hist
+
+
+def hist16_prefix(hist, prefix=None):
+    """Exclusive prefix of a 2^16-bin histogram: int64 tensor of 65537 (last = total)."""
+    _check_dev(hist)
+    prefix = torch.empty(65537, dtype=torch.int64, device=hist.device) if prefix is None else prefix
+    _check_dev(prefix)
+    st = lib().fs_hist16_prefix(_ptr(hist), _ptr(prefix), _stream(hist))
+    if st != FS_OK:
+        raise FsError(st, "fs_hist16_prefix")
+    return prefix
+
+
+def expand16(prefix, first, count, out=None):
+    """Sorted positions [first, first + count) of the multiset `prefix` describes."""
+    _check_dev(prefix)
+    out = torch.empty(int(count), dtype=torch.uint16, device=prefix.device) if out is None else out
+    _check_dev(out)
+    _u16(out, "out")
+    if out.numel() < count:
+        raise ValueError("out is shorter than count")
+    st = lib().fs_expand16(_ptr(prefix), int(first), int(count), _ptr(out), _stream(prefix))
+    if st != FS_OK:
+        raise FsError(st, "fs_expand16")
+    return out
+
+
+def sort16_host_workspace_bytes(batch_keys):
+    size = ctypes.c_size_t(0)
+    st = lib().fs_sort16_host(None, None, 0, int(batch_keys), None, ctypes.byref(size), None, None)
+    if st != FS_OK:
+        raise FsError(st, "fs_sort16_host (workspace query)")
+    return size.value
+
+
+def sort16_host(keys, out=None, batch_keys=1 << 26, workspace=None, copy_stream=None, device="cuda"):
+    """Sort 16-bit keys held in HOST memory (a CPU tensor, ideally pinned),
+    streaming them through the device in batches of `batch_keys`.  `out` may
+    be `keys` itself (in-place).  Blocks until `out` holds the result."""
+    for t in (keys,) + ((out,) if out is not None else ()):
+        if t.is_cuda or not t.is_contiguous():
+            raise ValueError("sort16_host takes contiguous host tensors")
+    _u16(keys, "keys")
+    out = torch.empty(keys.shape, dtype=keys.dtype, pin_memory=keys.is_pinned()) if out is None else out
+    _u16(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("keys and out differ in length")
+    dev = torch.device(device)
+    ws = workspace or Workspace(dev)
+    buf = ws.get(sort16_host_workspace_bytes(batch_keys))
+    size = ctypes.c_size_t(buf.numel())
+    xs = copy_stream if copy_stream is not None else torch.cuda.Stream(dev)
+    cs = torch.cuda.current_stream(dev)
+    st = lib().fs_sort16_host(_ptr(keys), _ptr(out), keys.numel(), int(batch_keys), _ptr(buf),
+                              ctypes.byref(size), ctypes.c_void_p(xs.cuda_stream),
+                              ctypes.c_void_p(cs.cuda_stream))
+    if st != FS_OK:
+        raise FsError(st, "fs_sort16_host")
+    return out

@@ -150,7 +150,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
                                                          part, wrap, wrap + kHist16Words, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part, L.hist_groups, wrap, wrap + kHist16Words, h16, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
-        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
+        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s));
         return FS_OK;
     }
 
@@ -197,7 +197,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
             FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, j == 1, s));
         }
         FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
-        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), n, s));
+        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s));
         return FS_OK;
     }
     FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));

@@ -41,7 +41,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStrea
 hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uint32_t* part,
                           uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s);
 hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t* wrap_lo,
-                          const uint32_t* wrap_word, uint64_t* h16, hipStream_t s);
+                          const uint32_t* wrap_word, uint64_t* h16, hipStream_t s,
+                          bool accumulate = false);
 hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s);
 hipError_t launch_plan_from16(const uint64_t* h16, uint64_t n, uint64_t* hist, uint64_t* base,
                               uint32_t* plan, hipStream_t s);
@@ -51,7 +52,9 @@ hipError_t launch_plan8(const uint32_t* part, uint32_t groups, int digits, uint6
                         uint64_t* hist, uint64_t* base, uint32_t* plan, hipStream_t s);
 hipError_t launch_reduce8(const uint32_t* part, uint32_t groups, int digits, uint64_t* hist,
                           hipStream_t s);
-hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t n, hipStream_t s);
+// writes sorted positions [first, first + count) (clipped to the total p16[65536]) to out
+hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, uint64_t count,
+                           hipStream_t s);
 hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
                           hipStream_t s);
 

@@ -103,6 +103,9 @@ hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uin
 
 // Sum the per-workgroup packed counters and repair wraps -> exact uint64
 // counts of all 2^16 bins (the global merge of Section III-A.1 / III-B).
+// With `accumulate` the counts are added to h16 instead of replacing it: the
+// histogram of a stream of batches is the sum of theirs (Section III-C).
+template <bool kAccumulate>
 __global__ __launch_bounds__(256) void k_merge16(const uint32_t* __restrict__ part, uint32_t groups,
                                                  const uint32_t* __restrict__ wrap_lo,
                                                  const uint32_t* __restrict__ wrap_word,
@@ -117,13 +120,22 @@ __global__ __launch_bounds__(256) void k_merge16(const uint32_t* __restrict__ pa
     }
     lo += (uint64_t)wrap_lo[w] << 16;
     all += (uint64_t)wrap_word[w] << 32;
-    h16[2 * w] = lo;
-    h16[2 * w + 1] = (all - lo) >> 16;
+    const uint64_t hi = (all - lo) >> 16;
+    if (kAccumulate) {
+        h16[2 * w] += lo;
+        h16[2 * w + 1] += hi;
+    } else {
+        h16[2 * w] = lo;
+        h16[2 * w + 1] = hi;
+    }
 }
 
 hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t* wrap_lo,
-                          const uint32_t* wrap_word, uint64_t* h16, hipStream_t s) {
-    k_merge16<<<kHist16Words / 256, 256, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
+                          const uint32_t* wrap_word, uint64_t* h16, hipStream_t s, bool accumulate) {
+    if (accumulate)
+        k_merge16<true><<<kHist16Words / 256, 256, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
+    else
+        k_merge16<false><<<kHist16Words / 256, 256, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
     return hipGetLastError();
 }
 
@@ -305,12 +317,21 @@ __device__ __forceinline__ uint32_t value_at(const uint64_t* p, uint32_t lo, uin
     return lo;
 }
 
+// Sorted positions [first, first + count) of the multiset whose exclusive
+// prefix is p16 (p16[65536] = total): position i holds the value v with
+// p16[v] <= i < p16[v + 1] (Algorithm 5 with no trailing bits, i.e. the
+// keys rebuilt from the leaf counters alone).  out[i - first] receives
+// position i; positions at or past the total are not written.
 template <bool kVec>
 __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __restrict__ p16,
-                                                             uint16_t* __restrict__ out, uint64_t n) {
+                                                             uint16_t* __restrict__ out, uint64_t first,
+                                                             uint64_t count) {
     __shared__ uint32_t window[2];
-    const uint64_t rs = (uint64_t)blockIdx.x * kExpandSpan;
-    const uint64_t re = rs + kExpandSpan < n ? rs + kExpandSpan : n;
+    const uint64_t total = p16[65536];
+    const uint64_t end = first + count < total ? first + count : total;
+    const uint64_t rs = first + (uint64_t)blockIdx.x * kExpandSpan;
+    if (rs >= end) return;
+    const uint64_t re = rs + kExpandSpan < end ? rs + kExpandSpan : end;
     if (threadIdx.x == 0) {
         window[0] = value_at(p16, 0, 65535, rs);
         window[1] = value_at(p16, 0, 65535, re - 1);
@@ -326,31 +347,33 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __r
         uint32_t o[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const uint64_t pos = p0 + e < n ? p0 + e : n - 1;
-            while (next <= pos) {  // p16[65536] = n > pos, so v stays <= 65535
+            const uint64_t pos = p0 + e < end ? p0 + e : end - 1;
+            while (next <= pos) {  // p16[65536] = total > pos, so v stays <= 65535
                 ++v;
                 next = p16[v + 1];
             }
             o[e] = v;
         }
-        if (kVec && p0 + 8 <= n) {
+        uint16_t* dst = out + (p0 - first);
+        if (kVec && p0 + 8 <= end) {
             u32x4 q;
             q.x = o[0] | (o[1] << 16);
             q.y = o[2] | (o[3] << 16);
             q.z = o[4] | (o[5] << 16);
             q.w = o[6] | (o[7] << 16);
-            __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out + p0));
+            __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(dst));
         } else {
-            for (int e = 0; e < 8 && p0 + e < n; ++e) out[p0 + e] = (uint16_t)o[e];
+            for (int e = 0; e < 8 && p0 + e < end; ++e) dst[e] = (uint16_t)o[e];
         }
     }
 }
 
-hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t n, hipStream_t s) {
-    const uint64_t groups = (n + kExpandSpan - 1) / kExpandSpan;
+hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const uint64_t groups = (count + kExpandSpan - 1) / kExpandSpan;
     const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-    if (vec) k_expand16<true><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, n);
-    else k_expand16<false><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, n);
+    if (vec) k_expand16<true><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, first, count);
+    else k_expand16<false><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, first, count);
     return hipGetLastError();
 }
 

@@ -1,0 +1,147 @@
+"""GPU parity of batch stream sorting of 16-bit keys (fs_hist16_accumulate,
+fs_hist16_prefix, fs_expand16, fs_sort16_host) against the oracle, byte for
+byte.
+
+A stream of batches is sorted exactly when the accumulated histogram equals
+the oracle's histogram of the concatenated batches, its prefix equals the
+oracle's exclusive scan, and every expanded range equals the same slice of
+the oracle's sort of the concatenation.  Batches are ragged, start at
+unaligned addresses, include empty and all-equal ones (the packed counters'
+wrap repair), and the host driver is run with batch sizes that leave a
+ragged last batch, with pinned and pageable memory and in place.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fsgen
+import oracle
+import paper_2605_10390_amd as fs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def _batches(seed):
+    """Ragged batches of every 16-bit distribution, plus an empty one and a
+    long all-equal one (more than 2^16 equal keys in one workgroup)."""
+    out = []
+    sizes = [1, 7, 4096 + 3, 65536 + 5, (1 << 20) + 11, 0, 300_001]
+    for i, n in enumerate(sizes):
+        dist = fsgen.DISTS_16[i % len(fsgen.DISTS_16)]
+        out.append(fsgen.keys_host(dist, 16, n, seed + i))
+    out.append(np.full(3 * 65536 + 9, 0xBEEF, dtype=np.uint16))
+    return out
+
+
+def test_accumulated_histogram_prefix_and_expansion(gpu):
+    ws = fs.Workspace(gpu)
+    batches = _batches(fsgen.seed_for(5, 0))
+    hist = fs.new_hist16(gpu)
+    for i, b in enumerate(batches):
+        # every other batch starts one key past a 16-byte boundary
+        t = dev(np.concatenate([np.zeros(1, np.uint16), b]))[1:] if i % 2 else dev(b)
+        fs.hist16_accumulate(t, hist, workspace=ws)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    allk = np.concatenate(batches)
+    want_h = oracle.histogram(allk, 0, 16)
+    assert np.array_equal(host(hist).view(np.uint64), want_h)
+
+    prefix = fs.hist16_prefix(hist)
+    want_p = oracle.exclusive_scan(want_h)
+    assert np.array_equal(host(prefix).view(np.uint64), want_p)
+
+    want = oracle.sort(allk)
+    n = allk.size
+    assert np.array_equal(host(fs.expand16(prefix, 0, n)), want)
+    # pieces in any order, unaligned starts and lengths
+    rng = np.random.default_rng(3)
+    cuts = np.sort(rng.choice(np.arange(1, n), size=40, replace=False))
+    bounds = [0, *cuts.tolist(), n]
+    pieces = list(zip(bounds[:-1], bounds[1:]))
+    rng.shuffle(pieces)
+    for a, b in pieces:
+        assert np.array_equal(host(fs.expand16(prefix, a, b - a)), want[a:b]), (a, b)
+
+
+def test_expansion_past_the_total_writes_nothing_there(gpu):
+    k = fsgen.keys_host("uniform", 16, 10_000, 17)
+    hist = fs.hist16_accumulate(dev(k), fs.new_hist16(gpu))
+    prefix = fs.hist16_prefix(hist)
+    out = dev(np.full(5000, 0x5A5A, np.uint16))
+    fs.expand16(prefix, 8000, 5000, out=out)
+    got = host(out)
+    assert np.array_equal(got[:2000], oracle.sort(k)[8000:])
+    assert np.all(got[2000:] == 0x5A5A)
+    # a range that starts past the total writes nothing
+    fs.expand16(prefix, 20_000, 100, out=out)
+    assert np.array_equal(host(out), got)
+
+
+def test_empty_histogram_expands_to_nothing(gpu):
+    hist = fs.new_hist16(gpu)
+    fs.hist16_accumulate(dev(np.zeros(0, np.uint16)), hist)
+    prefix = fs.hist16_prefix(hist)
+    assert int(prefix[-1].item()) == 0
+    out = dev(np.full(64, 7, np.uint16))
+    fs.expand16(prefix, 0, 64, out=out)
+    assert np.all(host(out) == 7)
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_host_stream_sort_matches_oracle(gpu, pinned):
+    ws = fs.Workspace(gpu)
+    for di, dist in enumerate(fsgen.DISTS_16):
+        n = 3 * (1 << 20) + 12_345
+        k = fsgen.keys_host(dist, 16, n, fsgen.seed_for(6, di))
+        src = torch.from_numpy(k)
+        if pinned:
+            src = src.pin_memory()
+        # batches of 2^20 + 3 keys (rounded up to a multiple of 8): ragged last batch
+        out = fs.sort16_host(src, batch_keys=(1 << 20) + 3, workspace=ws, device=gpu)
+        assert np.array_equal(out.numpy(), oracle.sort(k)), (dist, pinned)
+        # fewer keys than one batch
+        small = fs.sort16_host(src[:1000].clone(), batch_keys=1 << 16, workspace=ws, device=gpu)
+        assert np.array_equal(small.numpy(), oracle.sort(k[:1000]))
+
+
+def test_host_stream_sort_in_place_and_edges(gpu):
+    k = fsgen.keys_host("zipf", 16, 2_000_003, 29)
+    buf = torch.from_numpy(k.copy()).pin_memory()
+    fs.sort16_host(buf, out=buf, batch_keys=1 << 19, device=gpu)
+    assert np.array_equal(buf.numpy(), oracle.sort(k))
+    empty = torch.from_numpy(np.zeros(0, np.uint16))
+    assert fs.sort16_host(empty, device=gpu).numel() == 0
+    one = fs.sort16_host(torch.from_numpy(np.array([9], np.uint16)), batch_keys=1, device=gpu)
+    assert one.numpy().tolist() == [9]
+
+
+def test_host_stream_sort_large_is_sorted_permutation(gpu):
+    """2^30 host-resident keys (2 GiB) in 2^26-key batches: checked by
+    properties that fix the result at any size (non-decreasing, and the
+    same multiset as the input, counted on the CPU with numpy).  The keys
+    are drawn by the seeded device generator and copied to pinned memory."""
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint16, pin_memory=True)
+    src.copy_(fsgen.keys_device("uniform", 16, n, fsgen.seed_for(1, 0), device=gpu))
+    k = src.numpy().copy()
+    out = fs.sort16_host(src, batch_keys=1 << 26, device=gpu).numpy()
+    step = 1 << 26
+    counts_in = np.zeros(65536, np.int64)
+    counts_out = np.zeros(65536, np.int64)
+    for a in range(0, n, step):
+        o = out[a:a + step]
+        assert np.all(o[1:] >= o[:-1]), a
+        if a:
+            assert out[a - 1] <= o[0], a
+        counts_in += np.bincount(k[a:a + step], minlength=65536)
+        counts_out += np.bincount(o, minlength=65536)
+    assert np.array_equal(counts_in, counts_out)
