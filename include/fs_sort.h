@@ -55,7 +55,28 @@ typedef enum {
     FS_ERR_DEVICE = 4
 } fs_status;
 
-enum { FS_FLAG_NONE = 0 };
+/*
+ * Key order flags of fs_sort_keys / fs_sort_pairs (the paper sorts p-bit
+ * keys of any precision, Section I; these fix how the bits are compared).
+ * FS_FLAG_NONE: unsigned integers, ascending.
+ *   FS_FLAG_SIGNED      two's-complement signed integers.
+ *   FS_FLAG_FLOAT       IEEE 754 binary16 / binary32 / binary64 (for 16-bit
+ *                       keys also bfloat16, ordered by the same rule) in the
+ *                       standard's totalOrder: -NaN < -inf < negatives < -0
+ *                       < +0 < positives < +inf < +NaN, NaNs ordered by
+ *                       payload.  Bits are never changed, so NaN payloads
+ *                       and the sign of zero survive.
+ *   FS_FLAG_DESCENDING  largest key first.  Stability is kept: equal keys
+ *                       (same bits) stay in input order.
+ * SIGNED and FLOAT exclude each other; any other bit is FS_ERR_INVALID_ARG.
+ * fs_sort_segmented takes FS_FLAG_NONE only.
+ */
+enum {
+    FS_FLAG_NONE = 0,
+    FS_FLAG_SIGNED = 1,
+    FS_FLAG_FLOAT = 2,
+    FS_FLAG_DESCENDING = 4
+};
 
 /*
  * Stable ascending sort of n unsigned keys (Section II phases; for 16-bit
@@ -63,6 +84,7 @@ enum { FS_FLAG_NONE = 0 };
  * order, Algorithm 5 with no trailing bits).
  *   keys_in   device, n keys of key_bits bits (16, 32 or 64); not modified.
  *   keys_out  device, n keys; must not overlap keys_in.
+ *   flags     key order (FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING).
  */
 fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_bits,
                        unsigned flags, void *workspace, size_t *workspace_bytes, void *stream);
@@ -74,7 +96,8 @@ fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_
  * paper's index array (sorted position -> arrival position, Section III-G.3).
  *   keys_in/keys_out  device, n keys of key_bits bits (16, 32, 64).
  *   vals_in/vals_out  device, n values of val_bytes bytes (4 or 8).
- * None of the four ranges may overlap another.
+ * None of the four ranges may overlap another.  flags: key order, as for
+ * fs_sort_keys.
  */
 fs_status fs_sort_pairs(const void *keys_in, void *keys_out, const void *vals_in, void *vals_out,
                         uint64_t n, int key_bits, int val_bytes, unsigned flags,

@@ -13,6 +13,10 @@ Each function follows a passage of the paper (arXiv 2605.10390):
   sort            -- histogram / prefix / stable scatter radix sort
                      (Sec. II), least-significant 8-bit digit first
   sort_segments   -- independent sorts of back-to-back segments
+  sort_ordered    -- the same stable sort under another key order: signed
+                     integers, IEEE 754 totalOrder of floats, descending
+                     (the paper's keys of any precision, Sec. I); written
+                     from those orders' definitions, not from a bit mapping
 Every function is pinned by tests/test_oracle_pins.py against brute force,
 closed forms and library routines; none is "parity unpinned".
 """
@@ -129,3 +133,52 @@ def sort_segments(segments, lib=None):
         else:
             out.append(sort(seg, lib=lib))
     return out
+
+
+_SIGNED = {2: np.int16, 4: np.int32, 8: np.int64}
+_FLOAT = {2: np.float16, 4: np.float32, 8: np.float64}
+
+
+def _order_columns(keys, key_type):
+    """Sort columns for numpy.lexsort (last = most significant) that rank
+    `keys` (unsigned words) in the order of `key_type`."""
+    if key_type == "unsigned":
+        return [keys]
+    if key_type == "signed":
+        return [keys.view(_SIGNED[keys.itemsize])]
+    if key_type != "float":
+        raise ValueError(key_type)
+    # IEEE 754 totalOrder: negative NaNs (larger payload first), then the
+    # numbers by value with -0 before +0, then positive NaNs (smaller
+    # payload first)
+    f = keys.view(_FLOAT[keys.itemsize])
+    negative = np.signbit(f)
+    nan = np.isnan(f)
+    cls = np.where(nan, np.where(negative, 0, 2), 1)
+    value = np.where(nan, 0.0, f.astype(np.float64))
+    zero_sign = np.where((f == 0) & ~negative, 1, 0)
+    payload = (keys.astype(np.uint64) & np.uint64((1 << (8 * keys.itemsize - 1)) - 1)).astype(np.int64)
+    nan_rank = np.where(nan, np.where(negative, -payload, payload), 0)
+    return [nan_rank, zero_sign, value, cls]
+
+
+def sort_ordered(keys, vals=None, key_type="unsigned", descending=False):
+    """Stable sort of unsigned key words read as `key_type` ("unsigned",
+    "signed" two's complement, or "float" = IEEE 754 binary16/32/64 in
+    totalOrder), ascending or descending; equal keys (equal bits) keep their
+    input order either way.  Returns keys_out or (keys_out, vals_out)."""
+    keys = np.ascontiguousarray(keys)
+    n = keys.size
+    if descending:
+        # a stable ascending sort of the reversed input, read backwards
+        rev = keys[::-1].copy()
+        idx = np.lexsort(_order_columns(rev, key_type))
+        perm = (n - 1 - idx)[::-1]
+    else:
+        perm = np.lexsort(_order_columns(keys, key_type))
+    if vals is None:
+        return keys[perm]
+    vals = np.ascontiguousarray(vals)
+    if vals.size != n:
+        raise ValueError("keys and vals differ in length")
+    return keys[perm], vals[perm]

@@ -5,9 +5,12 @@ behind include/fs_sort.h.  PyTorch supplies device memory and the current
 stream.  There is no CPU fallback: if the HIP library is missing, every call
 raises.
 
-Keys are unsigned 16/32/64-bit integers (torch.uint16/uint32/uint64, or the
-signed dtypes of the same width, whose bits are then read as unsigned);
-values are 4- or 8-byte integers.  Results are ascending and stable.
+Keys are 16/32/64-bit integers or floats; values are 4- or 8-byte words.
+Results are stable (equal keys keep their input order).  The key order
+follows the dtype unless `key_type` says otherwise: unsigned dtypes sort as
+unsigned integers, signed dtypes as two's-complement integers, floating
+dtypes in IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf <
++NaN); `descending=True` reverses the order.
 """
 import ctypes
 import os
@@ -20,7 +23,10 @@ LIB_PATH = os.path.join(HERE, "libfsort.so")
 FS_OK, FS_ERR_INVALID_ARG, FS_ERR_UNSUPPORTED, FS_ERR_WORKSPACE_TOO_SMALL, FS_ERR_DEVICE = range(5)
 
 _KEY_BITS = {torch.uint16: 16, torch.int16: 16, torch.uint32: 32, torch.int32: 32,
-             torch.uint64: 64, torch.int64: 64}
+             torch.uint64: 64, torch.int64: 64, torch.float16: 16, torch.bfloat16: 16,
+             torch.float32: 32, torch.float64: 64}
+FS_FLAG_NONE, FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING = 0, 1, 2, 4
+_TYPE_FLAGS = {"unsigned": FS_FLAG_NONE, "signed": FS_FLAG_SIGNED, "float": FS_FLAG_FLOAT}
 _VAL_BYTES = {torch.uint32: 4, torch.int32: 4, torch.float32: 4, torch.uint64: 8,
               torch.int64: 8, torch.float64: 8}
 
@@ -99,6 +105,20 @@ def _key_bits(keys):
     return _KEY_BITS[keys.dtype]
 
 
+def order_flags(keys, key_type=None, descending=False):
+    """fs_sort flags for a key tensor: key_type None follows the dtype."""
+    if key_type is None:
+        if keys.dtype in (torch.int16, torch.int32, torch.int64):
+            key_type = "signed"
+        elif keys.dtype.is_floating_point:
+            key_type = "float"
+        else:
+            key_type = "unsigned"
+    if key_type not in _TYPE_FLAGS:
+        raise ValueError(f"key_type must be one of {sorted(_TYPE_FLAGS)}, not {key_type!r}")
+    return _TYPE_FLAGS[key_type] | (FS_FLAG_DESCENDING if descending else 0)
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(None)
 
@@ -140,8 +160,8 @@ def sort_pairs_workspace_bytes(n, key_bits, val_bytes):
     return size.value
 
 
-def sort_keys(keys, out=None, workspace=None):
-    """Ascending sort of a 1-D tensor of unsigned keys (returns `out`)."""
+def sort_keys(keys, out=None, workspace=None, key_type=None, descending=False):
+    """Stable sort of a 1-D key tensor (returns `out`); order per order_flags."""
     _check_dev(keys)
     bits = _key_bits(keys)
     n = keys.numel()
@@ -152,15 +172,16 @@ def sort_keys(keys, out=None, workspace=None):
     need = sort_keys_workspace_bytes(n, bits)
     buf = ws.get(need)
     size = ctypes.c_size_t(buf.numel())
-    st = lib().fs_sort_keys(_ptr(keys), _ptr(out), n, bits, 0, _ptr(buf), ctypes.byref(size),
-                            _stream(keys))
+    st = lib().fs_sort_keys(_ptr(keys), _ptr(out), n, bits, order_flags(keys, key_type, descending),
+                            _ptr(buf), ctypes.byref(size), _stream(keys))
     if st != FS_OK:
         raise FsError(st, "fs_sort_keys")
     return out
 
 
-def sort_pairs(keys, vals, keys_out=None, vals_out=None, workspace=None):
-    """Stable ascending sort of (key, value) pairs; returns (keys, values)."""
+def sort_pairs(keys, vals, keys_out=None, vals_out=None, workspace=None, key_type=None,
+               descending=False):
+    """Stable sort of (key, value) pairs; returns (keys, values); order per order_flags."""
     _check_dev(keys, vals)
     bits = _key_bits(keys)
     if vals.dtype not in _VAL_BYTES:
@@ -176,7 +197,8 @@ def sort_pairs(keys, vals, keys_out=None, vals_out=None, workspace=None):
     buf = ws.get(sort_pairs_workspace_bytes(n, bits, vb))
     size = ctypes.c_size_t(buf.numel())
     st = lib().fs_sort_pairs(_ptr(keys), _ptr(keys_out), _ptr(vals), _ptr(vals_out), n, bits, vb,
-                             0, _ptr(buf), ctypes.byref(size), _stream(keys))
+                             order_flags(keys, key_type, descending), _ptr(buf), ctypes.byref(size),
+                             _stream(keys))
     if st != FS_OK:
         raise FsError(st, "fs_sort_pairs")
     return keys_out, vals_out

@@ -98,10 +98,34 @@ constexpr uint64_t kMaxKeys = 1ull << 36;
 // enqueue `expr` (a launch) under the event recorder as kernel `kind`
 #define FS_LAUNCH(kind, keys, expr) FS_TRY(timed((kind), (keys), s, [&]() { return (expr); }))
 
+// Key order masks of order_map (fs_device.hpp) for the order flags; false
+// for an unknown flag or SIGNED together with FLOAT.
+static bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* neg) {
+    const unsigned known = FS_FLAG_SIGNED | FS_FLAG_FLOAT | FS_FLAG_DESCENDING;
+    if ((flags & ~known) || ((flags & FS_FLAG_SIGNED) && (flags & FS_FLAG_FLOAT))) return false;
+    const uint64_t all = key_bits == 64 ? ~0ull : (1ull << key_bits) - 1;
+    const uint64_t sign = 1ull << (key_bits - 1);
+    uint64_t p = 0, q = 0;
+    if (flags & FS_FLAG_SIGNED) p = q = sign;
+    if (flags & FS_FLAG_FLOAT) {
+        p = sign;
+        q = all;
+    }
+    if (flags & FS_FLAG_DESCENDING) {
+        p ^= all;
+        q ^= all;
+    }
+    *pos = p;
+    *neg = q;
+    return true;
+}
+
 static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
-                           uint64_t n, int key_bits, int val_bytes, void* workspace,
+                           uint64_t n, int key_bits, int val_bytes, unsigned flags, void* workspace,
                            size_t* workspace_bytes, hipStream_t s) {
     if (key_bits != 16 && key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
+    uint64_t opos = 0, oneg = 0;
+    if (!order_masks(flags, key_bits, &opos, &oneg)) return FS_ERR_INVALID_ARG;
     if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
     if (!workspace_bytes || n > kMaxKeys) return FS_ERR_INVALID_ARG;
     const int kb = key_bits / 8;
@@ -147,10 +171,12 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
         FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
         FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups,
-                                                         part, wrap, wrap + kHist16Words, s));
+                                                         part, wrap, wrap + kHist16Words, s, (uint32_t)opos,
+                                                         (uint32_t)oneg));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part, L.hist_groups, wrap, wrap + kHist16Words, h16, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
-        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s));
+        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s, (uint32_t)opos,
+                                                         (uint32_t)oneg));
         return FS_OK;
     }
 
@@ -175,6 +201,8 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     a.tickets = reinterpret_cast<uint32_t*>(w + L.tile_tickets);
     a.sink = w + L.sink;
     a.err = err;
+    a.ord_pos = opos;
+    a.ord_neg = oneg;
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
     if (L.pairs16) {
         // 16-bit keys with payloads: the first histogram is the compressed
@@ -197,7 +225,8 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
             FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, j == 1, s));
         }
         FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
-        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s));
+        FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s, (uint32_t)opos,
+                                                         (uint32_t)oneg));
         return FS_OK;
     }
     FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
@@ -218,17 +247,15 @@ extern "C" {
 
 fs_status fs_sort_keys(const void* keys_in, void* keys_out, uint64_t n, int key_bits, unsigned flags,
                        void* workspace, size_t* workspace_bytes, void* stream) {
-    if (flags != FS_FLAG_NONE) return FS_ERR_INVALID_ARG;
-    return fs::sort_impl(keys_in, keys_out, nullptr, nullptr, n, key_bits, 0, workspace,
+    return fs::sort_impl(keys_in, keys_out, nullptr, nullptr, n, key_bits, 0, flags, workspace,
                          workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 fs_status fs_sort_pairs(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
                         uint64_t n, int key_bits, int val_bytes, unsigned flags, void* workspace,
                         size_t* workspace_bytes, void* stream) {
-    if (flags != FS_FLAG_NONE) return FS_ERR_INVALID_ARG;
     if (val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
-    return fs::sort_impl(keys_in, keys_out, vals_in, vals_out, n, key_bits, val_bytes, workspace,
+    return fs::sort_impl(keys_in, keys_out, vals_in, vals_out, n, key_bits, val_bytes, flags, workspace,
                          workspace_bytes, static_cast<hipStream_t>(stream));
 }
 

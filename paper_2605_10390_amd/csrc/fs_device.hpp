@@ -65,6 +65,37 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
                           : __builtin_amdgcn_ubfe((uint32_t)(key >> 32), (uint32_t)(shift - 32), kRadixBits);
 }
 
+// Key order.  Signed, floating-point and descending sorts are unsigned
+// ascending sorts of a mapped key t = k ^ (top bit of k ? neg : pos), whose
+// unsigned order is the wanted order of k:
+//   unsigned  pos = neg = 0            signed  pos = neg = sign bit
+//   float     pos = sign bit, neg = all ones (IEEE 754 totalOrder: negative
+//             values have their magnitude bits reversed)
+//   descending: both masks complemented.
+// Kernels map keys where they load them and unmap them where they store
+// them, so memory only ever holds the caller's key bits; digits, counts and
+// ranks all refer to the mapped key.
+template <typename K>
+__device__ __forceinline__ K order_map(K k, K pos, K neg) {
+    return k ^ ((k >> (8 * sizeof(K) - 1)) ? neg : pos);
+}
+// the inverse: the mask applied was `neg` exactly when undoing it leaves
+// the top bit set
+template <typename K>
+__device__ __forceinline__ K order_unmap(K t, K pos, K neg) {
+    return t ^ (((K)(t ^ neg) >> (8 * sizeof(K) - 1)) ? neg : pos);
+}
+// order_map of every key packed in a 16-byte vector
+template <typename K>
+__device__ __forceinline__ u32x4 order_map_vec(u32x4 q, uint64_t pos, uint64_t neg) {
+    K k[16 / sizeof(K)];
+    __builtin_memcpy(k, &q, 16);
+#pragma unroll
+    for (int e = 0; e < (int)(16 / sizeof(K)); ++e) k[e] = order_map<K>(k[e], (K)pos, (K)neg);
+    __builtin_memcpy(&q, k, 16);
+    return q;
+}
+
 // Compressed 2^16-bin histogram of 16-bit keys in LDS.
 //
 // Counter pair w holds bin 2w in its low half and bin 2w+1 in its high half.

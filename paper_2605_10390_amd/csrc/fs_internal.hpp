@@ -38,8 +38,10 @@ int device_cu_count();
 // ---- launchers (each returns hipGetLastError after enqueueing) ----------
 hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStream_t s);
 
+// pos, neg: key order masks (order_map); 0, 0 counts the keys as they are
 hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uint32_t* part,
-                          uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s);
+                          uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s, uint32_t pos = 0,
+                          uint32_t neg = 0);
 hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t* wrap_lo,
                           const uint32_t* wrap_word, uint64_t* h16, hipStream_t s,
                           bool accumulate = false);
@@ -52,9 +54,10 @@ hipError_t launch_plan8(const uint32_t* part, uint32_t groups, int digits, uint6
                         uint64_t* hist, uint64_t* base, uint32_t* plan, hipStream_t s);
 hipError_t launch_reduce8(const uint32_t* part, uint32_t groups, int digits, uint64_t* hist,
                           hipStream_t s);
-// writes sorted positions [first, first + count) (clipped to the total p16[65536]) to out
+// writes sorted positions [first, first + count) (clipped to the total p16[65536]) to out,
+// each value unmapped with the key order masks pos, neg (order_unmap)
 hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, uint64_t count,
-                           hipStream_t s);
+                           hipStream_t s, uint32_t pos = 0, uint32_t neg = 0);
 hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
                           hipStream_t s);
 
@@ -84,6 +87,8 @@ struct TiledArgs {
     uint32_t* tickets;      // [passes][kXcds][kTicketStride] tile tickets, zero on entry
     void* sink;             // 16 bytes that absorb the stores of out-of-range lanes
     uint32_t* err;
+    uint64_t ord_pos = 0;   // key order masks (order_map); both 0: unsigned ascending
+    uint64_t ord_neg = 0;
 };
 
 ScatterShape tiled_shape(int key_bytes, int val_bytes);

@@ -35,9 +35,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStrea
 // Compressed 2^16-bin histogram of 16-bit keys, one per workgroup
 // (hist16_add, fs_device.hpp).
 // ----------------------------------------------------------------------------
+// With ORD the mapped keys are counted (order_map with masks opos, oneg).
+template <bool ORD>
 __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
     const uint16_t* __restrict__ keys, uint64_t n, uint64_t head, uint64_t nvec,
-    uint32_t* __restrict__ part, uint32_t* wrap_lo, uint32_t* wrap_word) {
+    uint32_t* __restrict__ part, uint32_t* wrap_lo, uint32_t* wrap_word, uint32_t opos, uint32_t oneg) {
     __shared__ uint32_t cnt[kHist16Words];
     const int tid = threadIdx.x;
     for (int i = tid; i < kHist16Words; i += kHist16Threads) cnt[i] = 0;
@@ -49,7 +51,8 @@ __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
     const uint64_t v1 = v0 + per < nvec ? v0 + per : nvec;
     const u32x4* vec = reinterpret_cast<const u32x4*>(keys + head);
     for (uint64_t v = v0 + tid; v < v1; v += kHist16Threads) {
-        const u32x4 q = __builtin_nontemporal_load(&vec[v]);
+        u32x4 q = __builtin_nontemporal_load(&vec[v]);
+        if constexpr (ORD) q = order_map_vec<uint16_t>(q, opos, oneg);
         const uint32_t w[4] = {q.x, q.y, q.z, q.w};
         // whole wave holding one key value: one add for all of it
         const uint32_t k0 = w[0] & 0xFFFFu;
@@ -83,7 +86,8 @@ __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
         const uint64_t extra = head + (n - tail0);
         for (uint64_t e = tid; e < extra; e += kHist16Threads) {
             const uint64_t i = e < head ? e : tail0 + (e - head);
-            hist16_add(cnt, keys[i], 1u, wrap_lo, wrap_word);
+            const uint16_t k = ORD ? order_map<uint16_t>(keys[i], (uint16_t)opos, (uint16_t)oneg) : keys[i];
+            hist16_add(cnt, k, 1u, wrap_lo, wrap_word);
         }
     }
     __syncthreads();
@@ -92,12 +96,15 @@ __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
 }
 
 hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uint32_t* part,
-                          uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s) {
+                          uint32_t* wrap_lo, uint32_t* wrap_word, hipStream_t s, uint32_t opos, uint32_t oneg) {
     const uintptr_t a = reinterpret_cast<uintptr_t>(keys);
     uint64_t head = ((16 - (a & 15)) & 15) / 2;
     if (head > n) head = n;
     const uint64_t nvec = (n - head) / 8;
-    k_hist16c<<<groups, kHist16Threads, 0, s>>>(keys, n, head, nvec, part, wrap_lo, wrap_word);
+    if (opos | oneg)
+        k_hist16c<true><<<groups, kHist16Threads, 0, s>>>(keys, n, head, nvec, part, wrap_lo, wrap_word, opos, oneg);
+    else
+        k_hist16c<false><<<groups, kHist16Threads, 0, s>>>(keys, n, head, nvec, part, wrap_lo, wrap_word, 0, 0);
     return hipGetLastError();
 }
 
@@ -321,11 +328,13 @@ __device__ __forceinline__ uint32_t value_at(const uint64_t* p, uint32_t lo, uin
 // prefix is p16 (p16[65536] = total): position i holds the value v with
 // p16[v] <= i < p16[v + 1] (Algorithm 5 with no trailing bits, i.e. the
 // keys rebuilt from the leaf counters alone).  out[i - first] receives
-// position i; positions at or past the total are not written.
-template <bool kVec>
+// position i; positions at or past the total are not written.  With ORD
+// the histogram counts mapped keys and each value is unmapped as it is
+// written (order_unmap with masks opos, oneg).
+template <bool kVec, bool ORD>
 __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __restrict__ p16,
                                                              uint16_t* __restrict__ out, uint64_t first,
-                                                             uint64_t count) {
+                                                             uint64_t count, uint32_t opos, uint32_t oneg) {
     __shared__ uint32_t window[2];
     const uint64_t total = p16[65536];
     const uint64_t end = first + count < total ? first + count : total;
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __r
                 ++v;
                 next = p16[v + 1];
             }
-            o[e] = v;
+            o[e] = ORD ? order_unmap<uint16_t>((uint16_t)v, (uint16_t)opos, (uint16_t)oneg) : v;
         }
         uint16_t* dst = out + (p0 - first);
         if (kVec && p0 + 8 <= end) {
@@ -368,12 +377,18 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __r
     }
 }
 
-hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, uint64_t count, hipStream_t s) {
+hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, uint64_t count, hipStream_t s,
+                           uint32_t opos, uint32_t oneg) {
     if (count == 0) return hipSuccess;
-    const uint64_t groups = (count + kExpandSpan - 1) / kExpandSpan;
+    const unsigned groups = (unsigned)((count + kExpandSpan - 1) / kExpandSpan);
     const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-    if (vec) k_expand16<true><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, first, count);
-    else k_expand16<false><<<(unsigned)groups, kExpandThreads, 0, s>>>(p16, out, first, count);
+    if (opos | oneg) {
+        if (vec) k_expand16<true, true><<<groups, kExpandThreads, 0, s>>>(p16, out, first, count, opos, oneg);
+        else k_expand16<false, true><<<groups, kExpandThreads, 0, s>>>(p16, out, first, count, opos, oneg);
+    } else {
+        if (vec) k_expand16<true, false><<<groups, kExpandThreads, 0, s>>>(p16, out, first, count, 0, 0);
+        else k_expand16<false, false><<<groups, kExpandThreads, 0, s>>>(p16, out, first, count, 0, 0);
+    }
     return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ __device__ __forceinline__ const K* pass_source(const TiledArgs& a, uint32_t sel
 constexpr int kHistCopies = 2;
 constexpr int kHistVecs = 4;  // 16-byte vectors per thread and step (plus one for misalignment)
 
-template <typename K, bool FIRST, int TILE>
+template <typename K, bool FIRST, int TILE, bool ORD>
 __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int pass) {
     constexpr int D = sizeof(K);
     constexpr int VK = 16 / sizeof(K);
@@ -108,6 +108,11 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         for (int r = 0; r <= kHistVecs; ++r) {
             const uint32_t v = tid + r * kTileHistThreads;
             if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
+        }
+        if constexpr (ORD) {  // count the mapped keys (order_map)
+#pragma unroll
+            for (int r = 0; r <= kHistVecs; ++r)
+                if (tid + r * kTileHistThreads < nv) q[r] = order_map_vec<K>(q[r], a.ord_pos, a.ord_neg);
         }
         // skewed digits: is the digit of the wave's first key shared by at
         // least kSkewLanes lanes in the step's first vector?  (wave-uniform;
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
 // the payloads.  One workgroup of kHist16Threads per CU (the counters take
 // 128 KiB of LDS).
 // ---------------------------------------------------------------------------
-template <int TILE>
+template <int TILE, bool ORD>
 __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uint32_t* __restrict__ part16,
                                                                  uint32_t* wrap_lo, uint32_t* wrap_word) {
     using K = uint16_t;
@@ -303,6 +308,11 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
         for (int r = 0; r <= kHistVecs; ++r) {
             const uint32_t v = tid + r * THREADS;
             if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
+        }
+        if constexpr (ORD) {  // count the mapped keys (order_map)
+#pragma unroll
+            for (int r = 0; r <= kHistVecs; ++r)
+                if (tid + r * THREADS < nv) q[r] = order_map_vec<K>(q[r], a.ord_pos, a.ord_neg);
         }
 #pragma unroll
         for (int r = 0; r <= kHistVecs; ++r) {
@@ -344,9 +354,9 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
                         st[e] = in ? (uint32_t)idx / TILE : 0u;
                         cc[e] = in ? 1u : 0u;
                         if (e == 0 || skewed) {
-                            uint32_t sh;
-                            cc[e] = leader_count((st[e] << 16) | kk[e], in, &sh);
-                            if (e == 0) skewed = sh >= kSkewLanes;
+                            uint32_t shared;
+                            cc[e] = leader_count((st[e] << 16) | kk[e], in, &shared);
+                            if (e == 0) skewed = shared >= kSkewLanes;
                         }
                     }
                     hist16_add_n<VK>(cnt, kk, cc, wrap_lo, wrap_word);
@@ -389,8 +399,11 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
 
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
                               uint32_t* wrap_word, hipStream_t s) {
-    if (a.tile == 4096) k_tile_hist16<4096><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
-    else return hipErrorInvalidValue;
+    if (a.tile != 4096) return hipErrorInvalidValue;
+    if (a.ord_pos | a.ord_neg)
+        k_tile_hist16<4096, true><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
+    else
+        k_tile_hist16<4096, false><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
     return hipGetLastError();
 }
 
@@ -499,7 +512,7 @@ __global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
 // a request and its use is fixed and the wait at the top of the loop leaves
 // the previous tile's stores in flight.
 // ---------------------------------------------------------------------------
-template <typename K, typename V, int THREADS, int ITEMS, bool LATE, bool SKIPK>
+template <typename K, typename V, int THREADS, int ITEMS, bool LATE, bool SKIPK, bool ORD>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_tile_scatter(TiledArgs a, int pass) {
     constexpr int W = THREADS / kWave;
@@ -610,7 +623,9 @@ void k_tile_scatter(TiledArgs a, int pass) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint32_t v = tid + r * THREADS;
-                if (v < nv) reinterpret_cast<u32x4*>(s_keys)[v] = nkv[r];
+                // ranks and digits refer to the mapped key (order_map)
+                if (v < nv)
+                    reinterpret_cast<u32x4*>(s_keys)[v] = ORD ? order_map_vec<K>(nkv[r], a.ord_pos, a.ord_neg) : nkv[r];
             }
             // payloads of this tile: copied out of the prefetch registers,
             // or (kLateVals) used from them directly, the next tile's
@@ -699,7 +714,7 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 bad_dst |= in && !(dst < a.n);
                 // SKIPK: the keys of this pass's output are written elsewhere
                 // (expanded from the 2^16-bin histogram)
-                if constexpr (!SKIPK) *(ok ? dst_k + dst : sink_k) = kk;
+                if constexpr (!SKIPK) *(ok ? dst_k + dst : sink_k) = ORD ? order_unmap<K>(kk, (K)a.ord_pos, (K)a.ord_neg) : kk;
                 if constexpr (kHasVals) *(ok ? dst_v + dst : sink_v) = s_vals[qq];
                 // keep the compiler from hoisting every slot's loads at once
                 if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -745,16 +760,22 @@ int tiled_scatter_per_cu(int key_bytes, int val_bytes) {
     hipError_t e = hipErrorInvalidValue;
 #define FS_OCC(K, V, THR, IT, LATE)                                                                  \
     if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>())                                   \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE, false>, THR, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE, false, false>, THR, 0);
     FS_TILED_SHAPES(FS_OCC)
 #undef FS_OCC
     return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
 }
 
+template <typename K, int TILE, bool ORD>
+static void launch_hist_o(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
+    if (pass == 0) k_tile_hist<K, true, TILE, ORD><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+    else k_tile_hist<K, false, TILE, ORD><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+}
+
 template <typename K, int TILE>
 static void launch_hist_t(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
-    if (pass == 0) k_tile_hist<K, true, TILE><<<groups, kTileHistThreads, 0, s>>>(a, pass);
-    else k_tile_hist<K, false, TILE><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+    if (a.ord_pos | a.ord_neg) launch_hist_o<K, TILE, true>(a, pass, groups, s);
+    else launch_hist_o<K, TILE, false>(a, pass, groups, s);
 }
 
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
@@ -781,10 +802,14 @@ hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes,
                                bool skip_keys, hipStream_t s) {
 #define FS_LAUNCH_SHAPE(K, V, THR, IT, LATE)                                              \
     if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>()) {                      \
-        if (skip_keys && sizeof(K) == 2 && val_size<V>() != 0)                            \
-            k_tile_scatter<K, V, THR, IT, LATE, true><<<groups, THR, 0, s>>>(a, pass);    \
-        else                                                                              \
-            k_tile_scatter<K, V, THR, IT, LATE, false><<<groups, THR, 0, s>>>(a, pass);   \
+        const bool ord = (a.ord_pos | a.ord_neg) != 0;                                    \
+        if (skip_keys && sizeof(K) == 2 && val_size<V>() != 0) {                          \
+            if (ord) k_tile_scatter<K, V, THR, IT, LATE, true, true><<<groups, THR, 0, s>>>(a, pass); \
+            else k_tile_scatter<K, V, THR, IT, LATE, true, false><<<groups, THR, 0, s>>>(a, pass);    \
+        } else {                                                                          \
+            if (ord) k_tile_scatter<K, V, THR, IT, LATE, false, true><<<groups, THR, 0, s>>>(a, pass); \
+            else k_tile_scatter<K, V, THR, IT, LATE, false, false><<<groups, THR, 0, s>>>(a, pass);    \
+        }                                                                                 \
         return hipGetLastError();                                                         \
     }
     FS_TILED_SHAPES(FS_LAUNCH_SHAPE)

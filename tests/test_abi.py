@@ -45,4 +45,8 @@ def test_argument_errors_need_no_gpu():
                                  ctypes.c_uint, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
     assert lib.fs_sort_keys(None, None, 10, 24, 0, None, ctypes.byref(size), None) == 1
-    assert lib.fs_sort_keys(None, None, 10, 16, 7, None, ctypes.byref(size), None) == 1
+    # SIGNED with FLOAT, and an unknown flag bit, are rejected; valid order flags are not
+    assert lib.fs_sort_keys(None, None, 10, 16, 3, None, ctypes.byref(size), None) == 1
+    assert lib.fs_sort_keys(None, None, 10, 16, 8, None, ctypes.byref(size), None) == 1
+    for flags in (1, 2, 4, 5, 6):
+        assert lib.fs_sort_keys(None, None, 10, 32, flags, None, ctypes.byref(size), None) == 0

@@ -1,0 +1,89 @@
+"""GPU parity of the key orders (FS_FLAG_SIGNED, FS_FLAG_FLOAT,
+FS_FLAG_DESCENDING) against oracle.sort_ordered, byte for byte.
+
+Every width takes both of its paths (16-bit keys-only: compressed histogram
+and expansion; 16-bit pairs: histogram, payload passes, expansion; wider
+keys: the 8-bit digit passes), over random bit patterns (for floats these
+include NaNs, infinities, subnormals and both zeros) with IEEE special
+values and repeated keys mixed in, sizes spanning several tiles with ragged
+tails, and all-equal keys (every digit trivial: a copy)."""
+import numpy as np
+import pytest
+import torch
+
+import fsgen
+import oracle
+import paper_2605_10390_amd as fs
+from tests.test_oracle_order_pins import TOTAL_ORDER_F16, TOTAL_ORDER_F32, _widen_f32_to_f64
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 63, 4097, 3 * 4096 + 17, 65536 + 123, (1 << 20) + 7]
+ORDERS = [("signed", False), ("signed", True), ("float", False), ("float", True), ("unsigned", True)]
+SPECIALS = {16: TOTAL_ORDER_F16, 32: TOTAL_ORDER_F32, 64: _widen_f32_to_f64(TOTAL_ORDER_F32)}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def _keys(bits, n, seed):
+    k = fsgen.keys_host("uniform", bits, n, seed)
+    if n >= 64:
+        sp = np.array(SPECIALS[bits], dtype=k.dtype)
+        rng = np.random.default_rng(seed)
+        pos = rng.choice(n, size=min(n // 4, 4 * sp.size), replace=False)
+        k[pos] = sp[np.arange(pos.size) % sp.size]
+        k[: n // 8] = k[n // 8: 2 * (n // 8)]  # repeats: stability
+    return k
+
+
+@pytest.mark.parametrize("bits", [16, 32, 64])
+@pytest.mark.parametrize("key_type,desc", ORDERS)
+def test_keys_in_every_order(gpu, bits, key_type, desc):
+    ws = fs.Workspace(gpu)
+    for n in SIZES:
+        k = _keys(bits, n, fsgen.seed_for(7, bits) + n)
+        out = fs.sort_keys(dev(k), workspace=ws, key_type=key_type, descending=desc)
+        torch.cuda.synchronize()
+        assert ws.error_word() == 0
+        assert np.array_equal(host(out), oracle.sort_ordered(k, key_type=key_type, descending=desc)), n
+
+
+@pytest.mark.parametrize("bits", [16, 32, 64])
+@pytest.mark.parametrize("key_type,desc", ORDERS)
+def test_pairs_in_every_order(gpu, bits, key_type, desc):
+    ws = fs.Workspace(gpu)
+    for n in SIZES:
+        k = _keys(bits, n, fsgen.seed_for(8, bits) + n)
+        v = fsgen.vals_host(n, 4)
+        ko, vo = fs.sort_pairs(dev(k), dev(v), workspace=ws, key_type=key_type, descending=desc)
+        ek, ev = oracle.sort_ordered(k, v, key_type=key_type, descending=desc)
+        assert ws.error_word() == 0
+        assert np.array_equal(host(ko), ek), n
+        assert np.array_equal(host(vo), ev), n
+
+
+def test_dtype_picks_the_order(gpu):
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(10_000).astype(np.float32)
+    out = fs.sort_keys(dev(f))
+    assert np.array_equal(host(out), np.sort(f))
+    i = rng.integers(-(1 << 40), 1 << 40, 10_000, dtype=np.int64)
+    assert np.array_equal(host(fs.sort_keys(dev(i), descending=True)), np.sort(i)[::-1])
+    h = rng.standard_normal(5000).astype(np.float16)
+    h[h == 0] = 1
+    assert np.array_equal(host(fs.sort_keys(dev(h))), np.sort(h))
+
+
+@pytest.mark.parametrize("bits", [16, 32, 64])
+def test_all_equal_keys_any_order(gpu, bits):
+    k = np.full(70_001, SPECIALS[bits][3], dtype=fsgen.key_dtype(bits))
+    v = fsgen.vals_host(k.size, 4)
+    for key_type, desc in ORDERS:
+        ko, vo = fs.sort_pairs(dev(k), dev(v), key_type=key_type, descending=desc)
+        assert np.array_equal(host(ko), k) and np.array_equal(host(vo), v)
