@@ -12,6 +12,8 @@ Each function follows a passage of the paper (arXiv 2605.10390):
                      histogram (Alg. 5 with no trailing bits)
   sort            -- histogram / prefix / stable scatter radix sort
                      (Sec. II), least-significant 8-bit digit first
+  sort_mt         -- `sort` split over threads (contiguous chunks, blocks
+                     laid out value-major then thread-minor), for timing
   sort_segments   -- independent sorts of back-to-back segments
   sort_ordered    -- the same stable sort under another key order: signed
                      integers, IEEE 754 totalOrder of floats, descending
@@ -54,6 +56,8 @@ def load(path=None, rebuild_if_missing=True):
     lib.oracle_expand.restype = i32
     lib.oracle_sort.argtypes = [vp, vp, vp, vp, u64, i32, i32]
     lib.oracle_sort.restype = i32
+    lib.oracle_sort_mt.argtypes = [vp, vp, vp, vp, u64, i32, i32, i32]
+    lib.oracle_sort_mt.restype = i32
     lib.oracle_sort_segments.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp, i32]
     lib.oracle_sort_segments.restype = i32
     if path is None:
@@ -121,6 +125,25 @@ def sort(keys, vals=None, lib=None):
     vo = np.empty_like(vals)
     _check(lib.oracle_sort(_ptr(keys), _ptr(ko), _ptr(vals), _ptr(vo), keys.size,
                            keys.itemsize, vals.itemsize), "sort")
+    return ko, vo
+
+
+def sort_mt(keys, vals=None, threads=4, lib=None):
+    """`sort` split over `threads` threads (for timing the CPU baseline);
+    byte-equal to `sort`."""
+    lib = lib or load()
+    keys = np.ascontiguousarray(keys)
+    ko = np.empty_like(keys)
+    if vals is None:
+        _check(lib.oracle_sort_mt(_ptr(keys), _ptr(ko), None, None, keys.size, keys.itemsize, 0, int(threads)),
+               "sort_mt")
+        return ko
+    vals = np.ascontiguousarray(vals)
+    if vals.size != keys.size:
+        raise ValueError("keys and vals differ in length")
+    vo = np.empty_like(vals)
+    _check(lib.oracle_sort_mt(_ptr(keys), _ptr(ko), _ptr(vals), _ptr(vo), keys.size, keys.itemsize,
+                              vals.itemsize, int(threads)), "sort_mt")
     return ko, vo
 
 

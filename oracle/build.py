@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(out_path=LIB, defines=(), opt="-O2"):
     """Compile oracle.c with gcc; `defines` plants mistakes for pin tests."""
-    cmd = ["gcc", opt, "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", SRC, "-o", out_path]
+    cmd = ["gcc", opt, "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread", SRC, "-o", out_path]
     cmd += ["-D" + d for d in defines]
     subprocess.run(cmd, check=True)
     return out_path

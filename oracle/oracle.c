@@ -26,9 +26,17 @@
  * digits and 64-bit counts: histogram, exclusive prefix, then a scatter that
  * walks the input in order, which is what makes it stable.
  *
- * Build: gcc -O2 -shared -fPIC oracle.c -o liboracle.so (see build.py).
+ * oracle_sort_mt is the same sort split over threads, for timing the CPU
+ * baseline only: each thread counts its contiguous chunk, the blocks are
+ * laid out digit value by digit value and, within one, thread by thread,
+ * and each thread then places its own chunk in order.  Chunks are in input
+ * order, so equal keys still keep their input order (tested byte-equal to
+ * oracle_sort).
+ *
+ * Build: gcc -O2 -shared -fPIC -pthread oracle.c -o liboracle.so (build.py).
  * Planted-mistake builds (tests only): -DORACLE_PLANT_<NAME>, see below.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -204,6 +212,107 @@ int oracle_sort(const void *keys_in, void *keys_out, const void *vals_in, void *
     if (val_bytes) memcpy(vals_out, vbuf[cur], n * (uint64_t)val_bytes);
     free(kbuf[0]); free(kbuf[1]); free(vbuf[0]); free(vbuf[1]);
     return ORACLE_OK;
+}
+
+#define ORACLE_MAX_THREADS 256
+
+struct mt_job {
+    const void *ks, *vs;
+    void *kd, *vd;
+    uint64_t lo, hi;
+    int key_bytes, val_bytes, shift;
+    uint64_t count[256]; /* this chunk's digit counts, then its next slots */
+};
+
+static void *mt_count(void *arg)
+{
+    struct mt_job *j = (struct mt_job *)arg;
+    memset(j->count, 0, sizeof j->count);
+    for (uint64_t i = j->lo; i < j->hi; ++i)
+        j->count[(key_at(j->ks, i, j->key_bytes) >> j->shift) & 0xFF]++;
+    return NULL;
+}
+
+static void *mt_place(void *arg)
+{
+    struct mt_job *j = (struct mt_job *)arg;
+    for (uint64_t i = j->lo; i < j->hi; ++i) {
+        uint64_t slot = j->count[(key_at(j->ks, i, j->key_bytes) >> j->shift) & 0xFF]++;
+        move_elem(j->kd, slot, j->ks, i, j->key_bytes);
+        if (j->val_bytes) move_elem(j->vd, slot, j->vs, i, j->val_bytes);
+    }
+    return NULL;
+}
+
+static int mt_run(void *(*fn)(void *), struct mt_job *jobs, int threads)
+{
+    pthread_t tid[ORACLE_MAX_THREADS];
+    int started = 0, rc = ORACLE_OK;
+    for (; started < threads; ++started)
+        if (pthread_create(&tid[started], NULL, fn, &jobs[started]) != 0) break;
+    for (int t = started; t < threads; ++t) fn(&jobs[t]); /* run here what could not start */
+    for (int t = 0; t < started; ++t)
+        if (pthread_join(tid[t], NULL) != 0) rc = ORACLE_BAD_ARG;
+    return rc;
+}
+
+/* oracle_sort over `threads` threads (1..ORACLE_MAX_THREADS); same result. */
+int oracle_sort_mt(const void *keys_in, void *keys_out, const void *vals_in, void *vals_out,
+                   uint64_t n, int key_bytes, int val_bytes, int threads)
+{
+    if (!valid_key_bytes(key_bytes) || threads < 1 || threads > ORACLE_MAX_THREADS) return ORACLE_BAD_ARG;
+    if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return ORACLE_BAD_ARG;
+    if (n && (!keys_in || !keys_out)) return ORACLE_BAD_ARG;
+    if (n && val_bytes && (!vals_in || !vals_out)) return ORACLE_BAD_ARG;
+    if (n == 0) return ORACLE_OK;
+    if ((uint64_t)threads > n) threads = (int)n;
+
+    void *kbuf[2], *vbuf[2] = {NULL, NULL};
+    kbuf[0] = malloc(n * (uint64_t)key_bytes);
+    kbuf[1] = malloc(n * (uint64_t)key_bytes);
+    if (val_bytes) {
+        vbuf[0] = malloc(n * (uint64_t)val_bytes);
+        vbuf[1] = malloc(n * (uint64_t)val_bytes);
+    }
+    struct mt_job *jobs = calloc((size_t)threads, sizeof *jobs);
+    if (!kbuf[0] || !kbuf[1] || (val_bytes && (!vbuf[0] || !vbuf[1])) || !jobs) {
+        free(kbuf[0]); free(kbuf[1]); free(vbuf[0]); free(vbuf[1]); free(jobs);
+        return ORACLE_NO_MEMORY;
+    }
+    memcpy(kbuf[0], keys_in, n * (uint64_t)key_bytes);
+    if (val_bytes) memcpy(vbuf[0], vals_in, n * (uint64_t)val_bytes);
+
+    int cur = 0, rc = ORACLE_OK;
+    for (int j = 0; j < key_bytes && rc == ORACLE_OK; ++j) {
+        for (int t = 0; t < threads; ++t) {
+            jobs[t].ks = kbuf[cur];
+            jobs[t].kd = kbuf[1 - cur];
+            jobs[t].vs = vbuf[cur];
+            jobs[t].vd = vbuf[1 - cur];
+            jobs[t].lo = n * (uint64_t)t / (uint64_t)threads;
+            jobs[t].hi = n * (uint64_t)(t + 1) / (uint64_t)threads;
+            jobs[t].key_bytes = key_bytes;
+            jobs[t].val_bytes = val_bytes;
+            jobs[t].shift = 8 * j;
+        }
+        rc = mt_run(mt_count, jobs, threads);
+        /* blocks: digit value major, thread minor (exclusive prefix) */
+        uint64_t run = 0;
+        for (int b = 0; b < 256; ++b)
+            for (int t = 0; t < threads; ++t) {
+                uint64_t c = jobs[t].count[b];
+                jobs[t].count[b] = run;
+                run += c;
+            }
+        if (rc == ORACLE_OK) rc = mt_run(mt_place, jobs, threads);
+        cur = 1 - cur;
+    }
+    if (rc == ORACLE_OK) {
+        memcpy(keys_out, kbuf[cur], n * (uint64_t)key_bytes);
+        if (val_bytes) memcpy(vals_out, vbuf[cur], n * (uint64_t)val_bytes);
+    }
+    free(kbuf[0]); free(kbuf[1]); free(vbuf[0]); free(vbuf[1]); free(jobs);
+    return rc;
 }
 
 /*

@@ -213,3 +213,22 @@ def test_planted_mistake_is_caught(plant):
         r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                            timeout=600)
         assert r.returncode != 0, f"no pin caught {plant}: {r.stdout[-500:]}"
+
+
+@pytest.mark.parametrize("key_bytes,val_bytes", [(2, 0), (2, 4), (4, 4), (8, 0), (8, 8)])
+def test_threaded_oracle_equals_single_thread(key_bytes, val_bytes):
+    """The CPU-baseline timing variant gives the same bytes as the oracle
+    for any thread count, including more threads than keys."""
+    rng = np.random.default_rng(key_bytes * 10 + val_bytes)
+    kdt = {2: np.uint16, 4: np.uint32, 8: np.uint64}[key_bytes]
+    for n in (0, 1, 5, 1000, 70_001):
+        k = rng.integers(0, 1 << 63, size=n, dtype=np.uint64).astype(kdt)
+        k[: n // 4] = k[n // 4: 2 * (n // 4)]
+        v = np.arange(n, dtype={4: np.uint32, 8: np.uint64}[val_bytes]) if val_bytes else None
+        want = oracle.sort(k, v)
+        for threads in (1, 3, 8, 64):
+            got = oracle.sort_mt(k, v, threads=threads)
+            if v is None:
+                assert np.array_equal(got, want), (n, threads)
+            else:
+                assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (n, threads)
