@@ -69,7 +69,7 @@ typedef enum {
  *   FS_FLAG_DESCENDING  largest key first.  Stability is kept: equal keys
  *                       (same bits) stay in input order.
  * SIGNED and FLOAT exclude each other; any other bit is FS_ERR_INVALID_ARG.
- * fs_sort_segmented takes FS_FLAG_NONE only.
+ * fs_sort_segmented applies the flags to every segment of the call.
  */
 enum {
     FS_FLAG_NONE = 0,
@@ -141,7 +141,9 @@ typedef struct {
  *   total_keys        sum of the segments' n (host-known, for sizing).
  *   max_segment_keys  the largest n (host-known, for sizing).
  * Segments may mix key widths and payload widths.  A segment's buffers must
- * not overlap each other or another segment's.
+ * not overlap each other or another segment's.  flags: the key order of
+ * every segment (FS_FLAG_SIGNED / FS_FLAG_FLOAT / FS_FLAG_DESCENDING, as for
+ * fs_sort_keys; each segment's sign bit is that of its own width).
  */
 fs_status fs_sort_segmented(const fs_segment *d_segments, uint32_t num_segments,
                             uint64_t total_keys, uint64_t max_segment_keys, unsigned flags,

@@ -340,20 +340,21 @@ class SegmentBatch:
     def workspace_bytes(self):
         return sort_segmented_workspace_bytes(self.count, self.total_keys, self.max_segment_keys)
 
-    def run(self, workspace=None, stream=None, tuning=None):
+    def run(self, workspace=None, stream=None, tuning=None, flags=FS_FLAG_NONE):
         """One fs_sort_segmented call (fs_sort_segmented_tuned when `tuning`
-        is given); returns the workspace."""
+        is given); `flags` is the key order of every segment (order_flags).
+        Returns the workspace."""
         ws = workspace or Workspace(self.d_desc.device)
         buf = ws.get(self.workspace_bytes())
         size = ctypes.c_size_t(buf.numel())
         s = stream if stream is not None else torch.cuda.current_stream(self.d_desc.device)
         if tuning is None:
             st = lib().fs_sort_segmented(_ptr(self.d_desc), self.count, self.total_keys,
-                                         self.max_segment_keys, 0, _ptr(buf), ctypes.byref(size),
+                                         self.max_segment_keys, flags, _ptr(buf), ctypes.byref(size),
                                          ctypes.c_void_p(s.cuda_stream))
         else:
             st = lib().fs_sort_segmented_tuned(_ptr(self.d_desc), self.count, self.total_keys,
-                                               self.max_segment_keys, 0, ctypes.byref(tuning), _ptr(buf),
+                                               self.max_segment_keys, flags, ctypes.byref(tuning), _ptr(buf),
                                                ctypes.byref(size), ctypes.c_void_p(s.cuda_stream))
         if st != FS_OK:
             raise FsError(st, "fs_sort_segmented")
@@ -387,10 +388,15 @@ class CapturedSort:
         self.graph.replay()
 
 
-def sort_segmented(segments, workspace=None, tuning=None):
+def sort_segmented(segments, workspace=None, tuning=None, key_type=None, descending=False):
     """Sort every (keys_in, keys_out, vals_in, vals_out) segment independently
-    in one call; returns the workspace (its error word is 0 on success)."""
-    return SegmentBatch(segments).run(workspace, tuning=tuning)
+    in one call; returns the workspace (its error word is 0 on success).
+    One key order holds for every segment: `key_type` None follows the key
+    dtypes, which must then agree on it (see order_flags)."""
+    flags = {order_flags(seg[0], key_type, descending) for seg in segments} or {FS_FLAG_NONE}
+    if len(flags) != 1:
+        raise ValueError("segments of one call share one key order; pass key_type explicitly")
+    return SegmentBatch(segments).run(workspace, tuning=tuning, flags=flags.pop())
 
 
 # ------------------------------------------------------- batch stream sorting

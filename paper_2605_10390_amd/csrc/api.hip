@@ -348,7 +348,10 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
                                   uint64_t max_segment_keys, unsigned flags, const fs_seg_tuning* tuning,
                                   void* workspace, size_t* workspace_bytes, void* stream) {
     using namespace fs;
-    if (flags != FS_FLAG_NONE || !workspace_bytes) return FS_ERR_INVALID_ARG;
+    if (!workspace_bytes) return FS_ERR_INVALID_ARG;
+    uint64_t opos[3], oneg[3];  // key order masks per width (16, 32, 64 bits)
+    for (int w = 0; w < 3; ++w)
+        if (!order_masks(flags, 16 << w, &opos[w], &oneg[w])) return FS_ERR_INVALID_ARG;
     fs_seg_tuning tune;
     if (tuning) {
         tune = *tuning;
@@ -396,6 +399,11 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(workspace);
     SegCtx x;
+    x.ord = flags != FS_FLAG_NONE;
+    for (int w = 0; w < 3; ++w) {
+        x.ord_pos[w] = opos[w];
+        x.ord_neg[w] = oneg[w];
+    }
     x.segs = d_segments;
     x.nseg = nseg;
     x.max_seg = max_segment_keys;

@@ -167,6 +167,9 @@ struct SegCtx {
     SegTileDesc* tdesc;     // [max_tiles]
     void* tmp_k;
     void* tmp_v;
+    uint32_t ord = 0;                 // nonzero: keys compare through order_map
+    uint64_t ord_pos[3] = {0, 0, 0};  // its masks per key width (16, 32, 64 bits)
+    uint64_t ord_neg[3] = {0, 0, 0};
 };
 uint32_t seg_max_tiles(uint64_t total_keys, uint32_t nseg);
 // checks a tuning's ranges (false: invalid)

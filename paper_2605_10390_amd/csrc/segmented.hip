@@ -59,6 +59,23 @@ __host__ __device__ inline int ctr_wg_taken(int c) { return 137 + c; }  //   and
 __host__ __device__ inline int ctr_wg_tmp(int c) { return 147 + 2 * c; }  // 64-bit temporary-pool bump (8-byte aligned)
 
 // ---------------------------------------------------------------------------
+// Key order of the call (order_map, fs_device.hpp): the kernels that touch
+// keys have an ORD instantiation, launched when x.ord is set, which maps keys
+// where they are loaded and unmaps them where they are stored; the other
+// instantiation passes keys through untouched.
+template <bool ORD, typename K>
+__device__ __forceinline__ K seg_map(const SegCtx& x, K k) {
+    constexpr int w = sizeof(K) == 2 ? 0 : sizeof(K) == 4 ? 1 : 2;
+    if constexpr (ORD) return order_map<K>(k, (K)x.ord_pos[w], (K)x.ord_neg[w]);
+    else return k;
+}
+template <bool ORD, typename K>
+__device__ __forceinline__ K seg_unmap(const SegCtx& x, K t) {
+    constexpr int w = sizeof(K) == 2 ? 0 : sizeof(K) == 4 ? 1 : 2;
+    if constexpr (ORD) return order_unmap<K>(t, (K)x.ord_pos[w], (K)x.ord_neg[w]);
+    else return t;
+}
+
 __global__ void k_seg_classify(SegCtx x) {
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < x.nseg; s += gridDim.x * blockDim.x) {
         const fs_segment d = x.segs[s];
@@ -177,8 +194,8 @@ __device__ __forceinline__ void lds_to_global(const T* lds, T* dst, uint32_t n) 
     }
 }
 
-template <typename K, typename V>
-__device__ __forceinline__ void sort_small(const fs_segment& d, SmallShared& sm) {
+template <typename K, typename V, bool ORD>
+__device__ __forceinline__ void sort_small(const SegCtx& x, const fs_segment& d, SmallShared& sm) {
     constexpr bool kHasVals = !__is_same(V, NoVal);
     using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
     constexpr int D = sizeof(K);
@@ -194,6 +211,10 @@ __device__ __forceinline__ void sort_small(const fs_segment& d, SmallShared& sm)
     global_to_lds<K, kSmallThreads>(static_cast<const K*>(d.keys_in), kbuf(0), n);
     if constexpr (kHasVals) global_to_lds<VS, kSmallThreads>(static_cast<const VS*>(d.vals_in), vbuf(0), n);
     __syncthreads();
+    if constexpr (ORD) {
+        for (uint32_t i = tid; i < n; i += kSmallThreads) kbuf(0)[i] = seg_map<ORD, K>(x, kbuf(0)[i]);
+        __syncthreads();
+    }
     int cur = 0;
     for (int j = 0; j < D; ++j) {
         const int shift = 8 * j;
@@ -249,11 +270,16 @@ __device__ __forceinline__ void sort_small(const fs_segment& d, SmallShared& sm)
         }
         cur = 1 - cur;
     }
+    if constexpr (ORD) {
+        for (uint32_t i = tid; i < n; i += kSmallThreads) kbuf(cur)[i] = seg_unmap<ORD, K>(x, kbuf(cur)[i]);
+        __syncthreads();
+    }
     lds_to_global<K, kSmallThreads>(kbuf(cur), static_cast<K*>(d.keys_out), n);
     if constexpr (kHasVals) lds_to_global<VS, kSmallThreads>(vbuf(cur), static_cast<VS*>(d.vals_out), n);
     __syncthreads();
 }
 
+template <bool ORD>
 __global__ __launch_bounds__(kSmallThreads) void k_seg_small(SegCtx x) {
     __shared__ SmallShared sm;
     const int tid = threadIdx.x;
@@ -272,15 +298,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_seg_small(SegCtx x) {
         if (i >= nsmall) break;
         const fs_segment d = x.segs[x.small_list[i]];
         switch (seg_class(d.key_bits / 8, d.val_bytes)) {
-        case 0: sort_small<uint16_t, NoVal>(d, sm); break;
-        case 1: sort_small<uint16_t, uint32_t>(d, sm); break;
-        case 2: sort_small<uint16_t, uint64_t>(d, sm); break;
-        case 3: sort_small<uint32_t, NoVal>(d, sm); break;
-        case 4: sort_small<uint32_t, uint32_t>(d, sm); break;
-        case 5: sort_small<uint32_t, uint64_t>(d, sm); break;
-        case 6: sort_small<uint64_t, NoVal>(d, sm); break;
-        case 7: sort_small<uint64_t, uint32_t>(d, sm); break;
-        default: sort_small<uint64_t, uint64_t>(d, sm); break;
+        case 0: sort_small<uint16_t, NoVal, ORD>(x, d, sm); break;
+        case 1: sort_small<uint16_t, uint32_t, ORD>(x, d, sm); break;
+        case 2: sort_small<uint16_t, uint64_t, ORD>(x, d, sm); break;
+        case 3: sort_small<uint32_t, NoVal, ORD>(x, d, sm); break;
+        case 4: sort_small<uint32_t, uint32_t, ORD>(x, d, sm); break;
+        case 5: sort_small<uint32_t, uint64_t, ORD>(x, d, sm); break;
+        case 6: sort_small<uint64_t, NoVal, ORD>(x, d, sm); break;
+        case 7: sort_small<uint64_t, uint32_t, ORD>(x, d, sm); break;
+        default: sort_small<uint64_t, uint64_t, ORD>(x, d, sm); break;
         }
     }
 }
@@ -396,7 +422,8 @@ __device__ __forceinline__ void exp_clear(ExpandShared& sm) {
 
 // histogram of keys [0, n) of `keys`: aligned 16-byte loads, keys outside
 // the range masked (an aligned 16-byte block never leaves a mapped page)
-__device__ __forceinline__ void exp_hist(ExpandShared& sm, const uint16_t* keys, uint64_t n) {
+template <bool ORD>
+__device__ __forceinline__ void exp_hist(const SegCtx& x, ExpandShared& sm, const uint16_t* keys, uint64_t n) {
     const int tid = threadIdx.x;
     const uintptr_t p = reinterpret_cast<uintptr_t>(keys);
     const uintptr_t a0 = p & ~(uintptr_t)15;
@@ -411,6 +438,10 @@ __device__ __forceinline__ void exp_hist(ExpandShared& sm, const uint16_t* keys,
         for (int u = 0; u < U; ++u) {
             const uint64_t i = i0 + (uint64_t)u * kExpThreads + tid;
             v[u] = __builtin_nontemporal_load(&vp[i < nv ? i : nv - 1]);
+        }
+        if constexpr (ORD) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = order_map_vec<uint16_t>(v[u], x.ord_pos[0], x.ord_neg[0]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -499,7 +530,8 @@ __device__ __forceinline__ void exp_scan(ExpandShared& sm) {
 // position with the last mark at or before it.  Every lane does the same
 // work, so no lane's walk holds the others up.  Lane i writes positions
 // 4i..4i+3 of the chunk with one aligned 8-byte store.
-__device__ __forceinline__ void exp_out(const ExpandShared& sm, uint16_t* out, uint64_t n, uint64_t pa,
+template <bool ORD>
+__device__ __forceinline__ void exp_out(const SegCtx& x, const ExpandShared& sm, uint16_t* out, uint64_t n, uint64_t pa,
                                         uint64_t pb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = kExpThreads / kWave;
@@ -621,7 +653,7 @@ __device__ __forceinline__ void exp_out(const ExpandShared& sm, uint16_t* out, u
         if (lane == 0) before = 0;
         uint32_t key[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) key[e] = vbase + (r[e] > before ? r[e] : before);
+        for (int e = 0; e < 4; ++e) key[e] = seg_unmap<ORD, uint16_t>(x, (uint16_t)(vbase + (r[e] > before ? r[e] : before)));
         const int64_t p0 = c0 + 4 * lane;
         if (p0 >= (int64_t)f && (uint64_t)(p0 + 4) <= cend) {
             const uint64_t qv = (uint64_t)key[0] | ((uint64_t)key[1] << 16) | ((uint64_t)key[2] << 32) |
@@ -641,6 +673,7 @@ __device__ __forceinline__ void exp_out(const ExpandShared& sm, uint16_t* out, u
 
 // medium segments: one workgroup per segment, queue entries popped one
 // segment ahead so that the pop and the descriptor load overlap the work
+template <bool ORD>
 __global__ __launch_bounds__(kExpThreads) void k_seg_expand16(SegCtx x) {
     __shared__ ExpandShared sm;
     const int tid = threadIdx.x;
@@ -659,13 +692,13 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_expand16(SegCtx x) {
         const fs_segment d = x.segs[x.expand_list[x.nseg - 1 - i]];
         exp_clear(sm);
         __syncthreads();
-        exp_hist(sm, static_cast<const uint16_t*>(d.keys_in), d.n);
+        exp_hist<ORD>(x, sm, static_cast<const uint16_t*>(d.keys_in), d.n);
         __syncthreads();
         exp_settle(sm, x.err);
         __syncthreads();
         exp_scan(sm);
         __syncthreads();
-        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, 0, d.n);
+        exp_out<ORD>(x, sm, static_cast<uint16_t*>(d.keys_out), d.n, 0, d.n);
     }
 }
 
@@ -723,6 +756,7 @@ __device__ __forceinline__ uint32_t x16_segment_of(const SegCtx& x, uint32_t par
     return q;
 }
 
+template <bool ORD>
 __global__ __launch_bounds__(kExpThreads) void k_seg_x16_hist(SegCtx x) {
     __shared__ ExpandShared sm;
     const int tid = threadIdx.x;
@@ -735,7 +769,7 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_x16_hist(SegCtx x) {
         const uint64_t m = d.n - b0 < kX16Part ? d.n - b0 : kX16Part;
         exp_clear(sm);
         __syncthreads();
-        exp_hist(sm, static_cast<const uint16_t*>(d.keys_in) + b0, m);
+        exp_hist<ORD>(x, sm, static_cast<const uint16_t*>(d.keys_in) + b0, m);
         __syncthreads();
         exp_settle(sm, x.err);
         __syncthreads();
@@ -753,6 +787,7 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_x16_hist(SegCtx x) {
     }
 }
 
+template <bool ORD>
 __global__ __launch_bounds__(kExpThreads) void k_seg_x16_out(SegCtx x) {
     __shared__ ExpandShared sm;
     const int tid = threadIdx.x;
@@ -788,7 +823,7 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_x16_out(SegCtx x) {
         __syncthreads();
         exp_scan(sm);
         __syncthreads();
-        exp_out(sm, static_cast<uint16_t*>(d.keys_out), d.n, pa, pb);
+        exp_out<ORD>(x, sm, static_cast<uint16_t*>(d.keys_out), d.n, pa, pb);
         __syncthreads();
     }
 }
@@ -855,7 +890,7 @@ __global__ void k_seg_tilemap(SegCtx x, int c) {
 // outside the range masked (an aligned 16-byte block never leaves a mapped
 // page); when every valid lane of a wave has the same digit (long runs of one
 // value, skewed keys) one lane adds the whole count.
-template <typename K>
+template <typename K, bool ORD>
 __global__ __launch_bounds__(kSegTileThreads) void k_seg_hist(SegCtx x, int c) {
     constexpr int D = sizeof(K);
     constexpr int VK = 16 / (int)sizeof(K);  // keys per vector
@@ -896,7 +931,7 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_hist(SegCtx x, int c) {
                 for (int e = 0; e < VK; ++e) {
                     const uint64_t idx = i * VK + e;
                     const bool valid = idx >= lead && idx < lead + count;
-                    const K key = kv[e];
+                    const K key = seg_map<ORD, K>(x, kv[e]);
 #pragma unroll
                     for (int j = 0; j < D; ++j) {
                         const uint32_t dg = digit_of<K>(key, 8 * j);
@@ -972,7 +1007,7 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegCtx x, int c) {
 // (tiles of THREADS * ITEMS keys; the tile layout used the same size).  The
 // first 256 threads also own one digit value each for the tile's counts,
 // its look-back and its output offsets.
-template <typename K, typename V, int THREADS, int ITEMS>
+template <typename K, typename V, int THREADS, int ITEMS, bool ORD>
 __global__ __launch_bounds__(THREADS) void k_seg_scatter(SegCtx x, int c, int j) {
     constexpr int W = THREADS / kWave;
     constexpr int T = THREADS * ITEMS;
@@ -1031,7 +1066,7 @@ __global__ __launch_bounds__(THREADS) void k_seg_scatter(SegCtx x, int c, int j)
             // every lane loads (clamped into the tile), so no load waits on a branch
             const uint32_t idx = wbase + k * kWave + lane;
             const uint32_t ic = idx < count ? idx : count - 1;
-            key[k] = src_k[tb + ic];
+            key[k] = seg_map<ORD, K>(x, src_k[tb + ic]);
             if constexpr (kHasVals) val[k] = src_v[tb + ic];
         }
         for (int i = 0; i < kRadix / kWave; ++i) s_wcnt[wave][lane + kWave * i] = 0;
@@ -1107,7 +1142,7 @@ __global__ __launch_bounds__(THREADS) void k_seg_scatter(SegCtx x, int c, int j)
                 const K kk = s_keys[qq];
                 const uint64_t o = s_delta[digit_of<K>(kk, shift)] + qq;
                 if (o < td.n) {
-                    dst_k[o] = kk;
+                    dst_k[o] = seg_unmap<ORD, K>(x, kk);
                     if constexpr (kHasVals) dst_v[o] = s_vals[qq];
                 } else {
                     atomicOr(x.err, 8u);
@@ -1124,7 +1159,7 @@ __global__ __launch_bounds__(THREADS) void k_seg_scatter(SegCtx x, int c, int j)
 // position from tile to tile in LDS: the stable scatter needs no look-back
 // and no workgroup waits for another.
 // ---------------------------------------------------------------------------
-template <typename K, typename V, int ITEMS>
+template <typename K, typename V, int ITEMS, bool ORD>
 __global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
     constexpr int THREADS = 256;
     constexpr int W = THREADS / kWave;
@@ -1190,9 +1225,10 @@ __global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
                     for (int e = 0; e < VK; ++e) {
                         const uint32_t idx = i * VK + e;
                         const bool valid = i < nv && idx >= lead && idx < lead + n;
+                        const K ke = seg_map<ORD, K>(x, kv[e]);
 #pragma unroll
                         for (int j = 0; j < D; ++j) {
-                            const uint32_t dg = digit_of<K>(kv[e], 8 * j);
+                            const uint32_t dg = digit_of<K>(ke, 8 * j);
                             const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
                             const uint64_t act = ballot(valid);
                             if (act != 0 && ballot(valid && dg == d0) == act) {
@@ -1248,7 +1284,7 @@ __global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
                 for (int k = 0; k < ITEMS; ++k) {
                     const uint32_t idx = wbase + k * kWave + lane;
                     const uint32_t ic = idx < count ? idx : count - 1;
-                    key[k] = to_global(src_k)[tb + ic];
+                    key[k] = seg_map<ORD, K>(x, to_global(src_k)[tb + ic]);
                     if constexpr (kHasVals) val[k] = to_global(src_v)[tb + ic];
                 }
                 for (int i = 0; i < kRadix / kWave; ++i) s_wcnt[wave][lane + kWave * i] = 0;
@@ -1295,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
                         const K kk = s_keys[qq];
                         const uint32_t o = s_delta[digit_of<K>(kk, shift)] + qq;
                         if (o < n) {
-                            to_global(dst_k)[o] = kk;
+                            to_global(dst_k)[o] = seg_unmap<ORD, K>(x, kk);
                             if constexpr (kHasVals) to_global(dst_v)[o] = s_vals[qq];
                         } else {
                             atomicOr(x.err, 8u);
@@ -1368,26 +1404,26 @@ __global__ void k_seg_zero_hist(SegCtx x, int c) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename K, typename V>
+template <typename K, typename V, bool ORD>
 static hipError_t run_class(const SegCtx& x, int c, int persistent, int threads, int items, hipStream_t s) {
     k_seg_zero_hist<<<1024, 256, 0, s>>>(x, c);
     k_seg_layout<<<1, 1024, 0, s>>>(x, c);
     k_seg_tilemap<<<256, 256, 0, s>>>(x, c);
-    k_seg_hist<K><<<persistent, kSegTileThreads, 0, s>>>(x, c);
+    k_seg_hist<K, ORD><<<persistent, kSegTileThreads, 0, s>>>(x, c);
     k_seg_scan<K><<<persistent, 256, 0, s>>>(x, c);
     k_seg_tiledesc<<<256, 256, 0, s>>>(x, c);
     for (int j = 0; j < (int)sizeof(K); ++j) {
         if (threads == 256) {
-            if (items == 8) k_seg_scatter<K, V, 256, 8><<<persistent, 256, 0, s>>>(x, c, j);
-            else k_seg_scatter<K, V, 256, 16><<<persistent, 256, 0, s>>>(x, c, j);
+            if (items == 8) k_seg_scatter<K, V, 256, 8, ORD><<<persistent, 256, 0, s>>>(x, c, j);
+            else k_seg_scatter<K, V, 256, 16, ORD><<<persistent, 256, 0, s>>>(x, c, j);
         } else {
-            if (items == 8) k_seg_scatter<K, V, 512, 8><<<persistent, 512, 0, s>>>(x, c, j);
-            else k_seg_scatter<K, V, 512, 16><<<persistent, 512, 0, s>>>(x, c, j);
+            if (items == 8) k_seg_scatter<K, V, 512, 8, ORD><<<persistent, 512, 0, s>>>(x, c, j);
+            else k_seg_scatter<K, V, 512, 16, ORD><<<persistent, 512, 0, s>>>(x, c, j);
         }
     }
     k_seg_copy<K, V><<<persistent, 256, 0, s>>>(x, c);
-    if (items == 8) k_seg_wg<K, V, 8><<<persistent, 256, 0, s>>>(x, c);
-    else k_seg_wg<K, V, 16><<<persistent, 256, 0, s>>>(x, c);
+    if (items == 8) k_seg_wg<K, V, 8, ORD><<<persistent, 256, 0, s>>>(x, c);
+    else k_seg_wg<K, V, 16, ORD><<<persistent, 256, 0, s>>>(x, c);
     return hipGetLastError();
 }
 
@@ -1402,6 +1438,30 @@ bool seg_tuning_valid(const fs_seg_tuning& t) {
            t.expand16_wgs_per_cu <= 2;
 }
 
+// every launch after the classification, in the key-order instantiation ORD
+template <bool ORD>
+static hipError_t launch_bins(const SegCtx& x, const fs_seg_tuning& t, int cus, hipStream_t s) {
+    const int xg = cus * (int)t.expand16_wgs_per_cu;
+    k_seg_x16_layout<<<1, 1024, 0, s>>>(x);
+    k_seg_x16_zero<<<1024, 256, 0, s>>>(x);
+    k_seg_x16_hist<ORD><<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_x16_out<ORD><<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_expand16<ORD><<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_small<ORD><<<cus * (int)t.small_wgs_per_cu, kSmallThreads, 0, s>>>(x);
+    const int P = cus * (int)t.large_wgs_per_cu;
+    const int it = (int)t.tile_items, th = (int)t.tile_threads;
+    hipError_t e;
+    if ((e = run_class<uint16_t, NoVal, ORD>(x, 0, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint16_t, uint32_t, ORD>(x, 1, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint16_t, uint64_t, ORD>(x, 2, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, NoVal, ORD>(x, 3, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, uint32_t, ORD>(x, 4, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint32_t, uint64_t, ORD>(x, 5, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint64_t, NoVal, ORD>(x, 6, P, th, it, s)) != hipSuccess) return e;
+    if ((e = run_class<uint64_t, uint32_t, ORD>(x, 7, P, th, it, s)) != hipSuccess) return e;
+    return run_class<uint64_t, uint64_t, ORD>(x, 8, P, th, it, s);
+}
+
 hipError_t launch_segmented(const SegCtx& x0, const fs_seg_tuning& t, hipStream_t s) {
     const int cus = device_cu_count();
     SegCtx x = x0;
@@ -1411,25 +1471,7 @@ hipError_t launch_segmented(const SegCtx& x0, const fs_seg_tuning& t, hipStream_
     x.split_min = t.expand16_split_keys < kX16MinSplit ? kX16MinSplit : t.expand16_split_keys;
     x.wg_max = t.large_wg_max_keys;
     k_seg_classify<<<(x.nseg + 255) / 256 < 1024 ? (x.nseg + 255) / 256 : 1024, 256, 0, s>>>(x);
-    const int xg = cus * (int)t.expand16_wgs_per_cu;
-    k_seg_x16_layout<<<1, 1024, 0, s>>>(x);
-    k_seg_x16_zero<<<1024, 256, 0, s>>>(x);
-    k_seg_x16_hist<<<xg, kExpThreads, 0, s>>>(x);
-    k_seg_x16_out<<<xg, kExpThreads, 0, s>>>(x);
-    k_seg_expand16<<<xg, kExpThreads, 0, s>>>(x);
-    k_seg_small<<<cus * (int)t.small_wgs_per_cu, kSmallThreads, 0, s>>>(x);
-    const int P = cus * (int)t.large_wgs_per_cu;
-    const int it = (int)t.tile_items, th = (int)t.tile_threads;
-    hipError_t e;
-    if ((e = run_class<uint16_t, NoVal>(x, 0, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint16_t, uint32_t>(x, 1, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint16_t, uint64_t>(x, 2, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, NoVal>(x, 3, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, uint32_t>(x, 4, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint32_t, uint64_t>(x, 5, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint64_t, NoVal>(x, 6, P, th, it, s)) != hipSuccess) return e;
-    if ((e = run_class<uint64_t, uint32_t>(x, 7, P, th, it, s)) != hipSuccess) return e;
-    return run_class<uint64_t, uint64_t>(x, 8, P, th, it, s);
+    return x.ord ? launch_bins<true>(x, t, cus, s) : launch_bins<false>(x, t, cus, s);
 }
 
 }  // namespace fs

@@ -87,3 +87,33 @@ def test_all_equal_keys_any_order(gpu, bits):
     for key_type, desc in ORDERS:
         ko, vo = fs.sort_pairs(dev(k), dev(v), key_type=key_type, descending=desc)
         assert np.array_equal(host(ko), k) and np.array_equal(host(vo), v)
+
+
+# (key bits, payload bytes, n): every bin of the segmented sort at the
+# default tuning -- the LDS bin, the 16-bit-digit bin (one workgroup, and
+# split into parts from 2^18 keys), the one-workgroup bin and the large bin
+SEGMENTS = [(16, 0, 100), (16, 0, 20_000), (16, 0, 300_001), (16, 4, 5_000), (16, 4, 200_003),
+            (32, 0, 3_000), (32, 0, 50_001), (32, 0, 400_007), (64, 4, 2_000), (64, 4, 100_003),
+            (64, 0, 300_001), (32, 8, 1), (64, 0, 0)]
+
+
+@pytest.mark.parametrize("key_type,desc", ORDERS)
+def test_segmented_in_every_order(gpu, key_type, desc):
+    rng = np.random.default_rng(11)
+    segs, want = [], []
+    for i, (bits, vb, n) in enumerate(SEGMENTS):
+        k = _keys(bits, n, fsgen.seed_for(9, i) + n)
+        v = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32 if vb == 4 else np.uint64) if vb else None
+        ki = dev(k)
+        vi = dev(v) if vb else None
+        segs.append((ki, torch.empty_like(ki), vi, torch.empty_like(vi) if vb else None))
+        want.append(oracle.sort_ordered(k, v, key_type=key_type, descending=desc))
+    ws = fs.sort_segmented(segs, key_type=key_type, descending=desc)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    for i, ((_, ko, _, vo), w) in enumerate(zip(segs, want)):
+        if vo is None:
+            assert np.array_equal(host(ko), w), SEGMENTS[i]
+        else:
+            assert np.array_equal(host(ko), w[0]), SEGMENTS[i]
+            assert np.array_equal(host(vo), w[1]), SEGMENTS[i]
