@@ -112,72 +112,113 @@ hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uin
 // counts of all 2^16 bins (the global merge of Section III-A.1 / III-B).
 // With `accumulate` the counts are added to h16 instead of replacing it: the
 // histogram of a stream of batches is the sum of theirs (Section III-C).
+// A block owns kMergeWords packed words; its eight 32-thread slices each sum
+// every eighth workgroup's copy, so the loads of a word are spread over the
+// whole GPU rather than queued in one thread.
+constexpr int kMergeWords = 32;
+constexpr int kMergeSlices = 8;
+
 template <bool kAccumulate>
-__global__ __launch_bounds__(256) void k_merge16(const uint32_t* __restrict__ part, uint32_t groups,
-                                                 const uint32_t* __restrict__ wrap_lo,
-                                                 const uint32_t* __restrict__ wrap_word,
-                                                 uint64_t* __restrict__ h16) {
-    const uint32_t w = blockIdx.x * 256 + threadIdx.x;
-    if (w >= (uint32_t)kHist16Words) return;
+__global__ __launch_bounds__(kMergeWords * kMergeSlices) void k_merge16(
+    const uint32_t* __restrict__ part, uint32_t groups, const uint32_t* __restrict__ wrap_lo,
+    const uint32_t* __restrict__ wrap_word, uint64_t* __restrict__ h16) {
+    __shared__ uint64_t s_lo[kMergeSlices][kMergeWords], s_all[kMergeSlices][kMergeWords];
+    const int tid = threadIdx.x, wl = tid % kMergeWords, slice = tid / kMergeWords;
+    const uint32_t w = blockIdx.x * kMergeWords + wl;
     uint64_t lo = 0, all = 0;
-    for (uint32_t g = 0; g < groups; ++g) {
+#pragma unroll 4
+    for (uint32_t g = slice; g < groups; g += kMergeSlices) {
         const uint32_t x = part[(uint64_t)g * kHist16Words + w];
         lo += x & 0xFFFFu;
         all += x;
     }
-    lo += (uint64_t)wrap_lo[w] << 16;
-    all += (uint64_t)wrap_word[w] << 32;
-    const uint64_t hi = (all - lo) >> 16;
-    if (kAccumulate) {
-        h16[2 * w] += lo;
-        h16[2 * w + 1] += hi;
-    } else {
-        h16[2 * w] = lo;
-        h16[2 * w + 1] = hi;
+    s_lo[slice][wl] = lo;
+    s_all[slice][wl] = all;
+    __syncthreads();
+    if (tid < kMergeWords) {
+        lo = 0;
+        all = 0;
+#pragma unroll
+        for (int k = 0; k < kMergeSlices; ++k) {
+            lo += s_lo[k][tid];
+            all += s_all[k][tid];
+        }
+        lo += (uint64_t)wrap_lo[w] << 16;
+        all += (uint64_t)wrap_word[w] << 32;
+        const uint64_t hi = (all - lo) >> 16;
+        if (kAccumulate) {
+            h16[2 * w] += lo;
+            h16[2 * w + 1] += hi;
+        } else {
+            h16[2 * w] = lo;
+            h16[2 * w + 1] = hi;
+        }
     }
 }
 
 hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t* wrap_lo,
                           const uint32_t* wrap_word, uint64_t* h16, hipStream_t s, bool accumulate) {
+    constexpr unsigned blocks = kHist16Words / kMergeWords, threads = kMergeWords * kMergeSlices;
     if (accumulate)
-        k_merge16<true><<<kHist16Words / 256, 256, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
+        k_merge16<true><<<blocks, threads, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
     else
-        k_merge16<false><<<kHist16Words / 256, 256, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
+        k_merge16<false><<<blocks, threads, 0, s>>>(part, groups, wrap_lo, wrap_word, h16);
     return hipGetLastError();
 }
 
 // Exclusive prefix of the 2^16 bins (GetIndex of every value, Algorithm 3):
-// p16[v] = sum(h16[0..v-1]), p16[65536] = n.  One block of 1024 threads,
-// 64 consecutive bins per thread.
-__global__ __launch_bounds__(1024) void k_scan16(const uint64_t* __restrict__ h16,
-                                                 uint64_t* __restrict__ p16) {
-    __shared__ uint64_t wsum[16];
+// p16[v] = sum(h16[0..v-1]), p16[65536] = n.  Block b of kScanBlocks owns
+// bins [1024 b, 1024 b + 1024), one per thread; it sums all bins before its
+// own (the whole histogram is 512 KiB and is read from L2), then scans its
+// own bins.  No block waits for another.
+constexpr int kScanThreads = 1024;
+constexpr int kScanBlocks = 65536 / kScanThreads;
+
+// exclusive scan of one value per thread over a block of kScanThreads; *total gets the sum
+__device__ __forceinline__ uint64_t scan_block1024(uint64_t x, uint64_t* wsum, uint64_t* total) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t* h = h16 + tid * 64;
-    uint64_t local = 0;
-    for (int i = 0; i < 64; ++i) local += h[i];
-    uint64_t inc = local;
+    uint64_t inc = x;
+#pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        uint64_t y = __shfl_up(inc, off, 64);
+        const uint64_t y = __shfl_up(inc, off, 64);
         if (lane >= off) inc += y;
     }
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    uint64_t before = 0, total = 0;
-    for (int w = 0; w < 16; ++w) {
-        if (w < wave) before += wsum[w];
-        total += wsum[w];
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const uint64_t v = wsum[w];
+        if (w < wave) before += v;
+        all += v;
     }
-    uint64_t run = before + inc - local;
-    for (int i = 0; i < 64; ++i) {
-        p16[tid * 64 + i] = run;
-        run += h[i];
-    }
-    if (tid == 0) p16[65536] = total;
+    *total = all;
+    return before + inc - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan16(const uint64_t* __restrict__ h16,
+                                                         uint64_t* __restrict__ p16) {
+    __shared__ uint64_t wsum[kScanThreads / 64];
+    __shared__ uint64_t wsum2[kScanThreads / 64];
+    const int tid = threadIdx.x;
+    const uint32_t b = blockIdx.x;
+    // sum of the bins of all earlier blocks
+    uint64_t acc = 0;
+#pragma unroll 4
+    for (uint32_t i = tid; i < b * kScanThreads; i += kScanThreads) acc += h16[i];
+    uint64_t base;
+    (void)scan_block1024(acc, wsum, &base);
+    // this block's bins
+    const uint32_t v = b * kScanThreads + tid;
+    const uint64_t c = h16[v];
+    uint64_t total;
+    const uint64_t excl = scan_block1024(c, wsum2, &total);
+    p16[v] = base + excl;
+    if (v == 65535) p16[65536] = base + total;
 }
 
 hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s) {
-    k_scan16<<<1, 1024, 0, s>>>(h16, p16);
+    k_scan16<<<kScanBlocks, kScanThreads, 0, s>>>(h16, p16);
     return hipGetLastError();
 }
 
