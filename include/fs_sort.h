@@ -104,6 +104,32 @@ fs_status fs_sort_pairs(const void *keys_in, void *keys_out, const void *vals_in
                         void *workspace, size_t *workspace_bytes, void *stream);
 
 /*
+ * Keys wider than 64 bits (the paper sorts keys of any precision p,
+ * Section I; its radix passes run over the key from the least significant
+ * digit up, Section II).  A key is key_words 64-bit words, word 0 the least
+ * significant, so key i occupies words [i * key_words, (i + 1) * key_words)
+ * of keys_in (little-endian throughout: a key is one little-endian integer
+ * of 64 * key_words bits).  key_words is 1..64; 1 is the 64-bit sort.
+ * The sort runs one round per word, least significant first: each round
+ * stably sorts that word (order-mapped) paired with the permutation so far,
+ * and the last permutation moves whole keys and payloads.  Results are
+ * those of fs_sort_keys / fs_sort_pairs for a key of that width: stable,
+ * in the order `flags` gives (FS_FLAG_SIGNED: two's complement over the
+ * whole width; FS_FLAG_FLOAT: sign-magnitude over the whole width, e.g.
+ * IEEE binary128 for two words; FS_FLAG_DESCENDING).
+ *   keys_in / keys_out  device, n * key_words uint64 words, 8-byte aligned,
+ *                       not overlapping.
+ *   vals_in / vals_out  device, n values of val_bytes bytes (4 or 8).
+ * The workspace holds two permutations, two word arrays and the workspace
+ * of a 64-bit pair sort of n elements.
+ */
+fs_status fs_sort_keys_wide(const void *keys_in, void *keys_out, uint64_t n, int key_words, unsigned flags,
+                            void *workspace, size_t *workspace_bytes, void *stream);
+fs_status fs_sort_pairs_wide(const void *keys_in, void *keys_out, const void *vals_in, void *vals_out,
+                             uint64_t n, int key_words, int val_bytes, unsigned flags, void *workspace,
+                             size_t *workspace_bytes, void *stream);
+
+/*
  * Leaf counters of every digit of the keys (the histogram of Section III-B,
  * Algorithm 1, merged across workgroups as in Section III-A.1/III-B):
  *   hist_out[j * 2^digit_bits + b] = #{ i : bits [j*digit_bits,

@@ -15,6 +15,9 @@ Each function follows a passage of the paper (arXiv 2605.10390):
   sort_mt         -- `sort` split over threads (contiguous chunks, blocks
                      laid out value-major then thread-minor), for timing
   sort_segments   -- independent sorts of back-to-back segments
+  sort_wide       -- stable sort of keys of several 64-bit words, compared
+                     as Python integers of the whole width (unsigned,
+                     two's complement, or sign-magnitude)
   sort_ordered    -- the same stable sort under another key order: signed
                      integers, IEEE 754 totalOrder of floats, descending
                      (the paper's keys of any precision, Sec. I); written
@@ -205,3 +208,35 @@ def sort_ordered(keys, vals=None, key_type="unsigned", descending=False):
     if vals.size != n:
         raise ValueError("keys and vals differ in length")
     return keys[perm], vals[perm]
+
+
+def _wide_value(words, key_type):
+    """A key of 64-bit words (least significant first) as a sortable Python
+    value of the whole width."""
+    bits = 64 * len(words)
+    v = 0
+    for i, w in enumerate(words):
+        v |= int(w) << (64 * i)
+    if key_type == "unsigned":
+        return v
+    if key_type == "signed":
+        return v - (1 << bits) if v >> (bits - 1) else v
+    if key_type == "float":
+        # sign-magnitude total order: negatives by falling magnitude, -0 before +0
+        mag = v & ((1 << (bits - 1)) - 1)
+        return (0, -mag) if v >> (bits - 1) else (1, mag)
+    raise ValueError(key_type)
+
+
+def sort_wide(keys, vals=None, key_type="unsigned", descending=False):
+    """Stable sort of an (n, W) uint64 array of keys (word 0 least
+    significant) by the whole-width value of `key_type`; equal keys keep
+    their input order in either direction.  Returns keys_out or
+    (keys_out, vals_out)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    vals_of = [_wide_value(row, key_type) for row in keys]
+    order = sorted(range(keys.shape[0]), key=lambda i: vals_of[i], reverse=descending)
+    if vals is None:
+        return keys[order]
+    vals = np.ascontiguousarray(vals)
+    return keys[order], vals[order]

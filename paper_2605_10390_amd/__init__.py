@@ -69,6 +69,10 @@ def lib():
     L.fs_profile_read.argtypes = [i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
                                   ctypes.POINTER(ctypes.c_double)]
     L.fs_profile_read.restype = i32
+    L.fs_sort_keys_wide.argtypes = [vp, vp, u64, i32, ctypes.c_uint, vp, sz, vp]
+    L.fs_sort_keys_wide.restype = i32
+    L.fs_sort_pairs_wide.argtypes = [vp, vp, vp, vp, u64, i32, i32, ctypes.c_uint, vp, sz, vp]
+    L.fs_sort_pairs_wide.restype = i32
     L.fs_hist16_accumulate.argtypes = [vp, u64, vp, vp, sz, vp]
     L.fs_hist16_accumulate.restype = i32
     L.fs_hist16_prefix.argtypes = [vp, vp, vp]
@@ -225,6 +229,53 @@ def digit_histograms(keys, digit_bits=8, workspace=None):
     if st != FS_OK:
         raise FsError(st, "fs_digit_histograms")
     return out
+
+
+def sort_wide(keys, vals=None, keys_out=None, vals_out=None, workspace=None, key_type="unsigned",
+              descending=False):
+    """Stable sort of keys wider than 64 bits: `keys` is an (n, W) tensor of
+    64-bit words (int64 or uint64), word 0 the least significant.  Returns
+    keys_out, or (keys_out, vals_out) when `vals` is given.  key_type is
+    "unsigned", "signed" (two's complement over the whole width) or "float"
+    (sign-magnitude over the whole width)."""
+    if keys.dim() != 2 or keys.dtype not in (torch.int64, torch.uint64):
+        raise ValueError("keys must be an (n, words) tensor of 64-bit words")
+    _check_dev(keys)
+    n, words = keys.shape
+    if key_type not in _TYPE_FLAGS:
+        raise ValueError(f"key_type must be one of {sorted(_TYPE_FLAGS)}, not {key_type!r}")
+    flags = _TYPE_FLAGS[key_type] | (FS_FLAG_DESCENDING if descending else 0)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    _check_dev(keys_out)
+    L = lib()
+    size = ctypes.c_size_t(0)
+    vb = 0
+    if vals is not None:
+        _check_dev(vals)
+        if vals.dtype not in _VAL_BYTES or vals.numel() != n:
+            raise ValueError("vals must hold one 4- or 8-byte value per key")
+        vb = _VAL_BYTES[vals.dtype]
+        vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+        _check_dev(vals_out)
+        st = L.fs_sort_pairs_wide(None, None, None, None, n, words, vb, flags, None, ctypes.byref(size), None)
+    else:
+        st = L.fs_sort_keys_wide(None, None, n, words, flags, None, ctypes.byref(size), None)
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_*_wide (workspace query)")
+    ws = workspace or Workspace(keys.device)
+    buf = ws.get(size.value)
+    size = ctypes.c_size_t(buf.numel())
+    if vals is not None:
+        st = L.fs_sort_pairs_wide(_ptr(keys), _ptr(keys_out), _ptr(vals), _ptr(vals_out), n, words, vb, flags,
+                                  _ptr(buf), ctypes.byref(size), _stream(keys))
+        if st != FS_OK:
+            raise FsError(st, "fs_sort_pairs_wide")
+        return keys_out, vals_out
+    st = L.fs_sort_keys_wide(_ptr(keys), _ptr(keys_out), n, words, flags, _ptr(buf), ctypes.byref(size),
+                             _stream(keys))
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_keys_wide")
+    return keys_out
 
 
 # ------------------------------------------------------------- segmented sort

@@ -16,7 +16,7 @@ BUILD_DIR = os.path.join(ROOT, "_build", "fsort")
 LIB = os.path.join(HERE, "libfsort.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hist.hip", "tiled.hip", "segmented.hip", "stream.hip", "api.hip", "profile.hip"]
+SOURCES = ["hist.hip", "tiled.hip", "segmented.hip", "stream.hip", "wide.hip", "api.hip", "profile.hip"]
 HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]

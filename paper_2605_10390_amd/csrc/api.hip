@@ -241,6 +241,95 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     return FS_OK;
 }
 
+// Keys of `words` 64-bit words (word 0 least significant), sorted least
+// significant word first: each round gathers one word of every key through
+// the current permutation (mapped into the requested order) and stably sorts
+// (word, permutation entry) pairs with sort_impl; the last permutation then
+// moves whole keys and payloads.  Stable rounds from the lowest word up
+// order keys by the highest word first, ties by the lower words, then by
+// input position.
+constexpr int kMaxKeyWords = 64;
+
+static fs_status sort_wide_impl(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
+                                uint64_t n, int words, int val_bytes, unsigned flags, void* workspace,
+                                size_t* workspace_bytes, hipStream_t s) {
+    if (words < 1 || words > kMaxKeyWords) return FS_ERR_INVALID_ARG;
+    if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
+    if (!workspace_bytes || n > kMaxKeys) return FS_ERR_INVALID_ARG;
+    if (words == 1)  // one word is a 64-bit key
+        return sort_impl(keys_in, keys_out, vals_in, vals_out, n, 64, val_bytes, flags, workspace,
+                         workspace_bytes, s);
+    // order masks per word: the top word carries the sign; a float's other
+    // words are complemented when it is negative
+    const unsigned known = FS_FLAG_SIGNED | FS_FLAG_FLOAT | FS_FLAG_DESCENDING;
+    if ((flags & ~known) || ((flags & FS_FLAG_SIGNED) && (flags & FS_FLAG_FLOAT))) return FS_ERR_INVALID_ARG;
+    const uint64_t sign = 1ull << 63;
+    auto word_masks = [&](int w, uint64_t* pos, uint64_t* neg) {
+        uint64_t p = 0, q = 0;
+        if (w == words - 1 && (flags & FS_FLAG_SIGNED)) p = q = sign;
+        if (flags & FS_FLAG_FLOAT) {
+            p = w == words - 1 ? sign : 0;
+            q = ~0ull;
+        }
+        if (flags & FS_FLAG_DESCENDING) {
+            p = ~p;
+            q = ~q;
+        }
+        *pos = p;
+        *neg = q;
+    };
+    const int pb = n > 0xFFFFFFFFull ? 8 : 4;  // permutation entry width
+    size_t inner = 0;
+    {
+        const fs_status st = sort_impl(nullptr, nullptr, nullptr, nullptr, n, 64, pb, 0, nullptr, &inner, s);
+        if (st != FS_OK) return st;
+    }
+    // the inner sort's workspace comes first, so word 0 is its error word
+    const size_t o_inner = 0;
+    const size_t o_perm0 = align_up(inner, 256);
+    const size_t o_perm1 = o_perm0 + align_up(std::max<uint64_t>(n, 1) * pb, 256);
+    const size_t o_word0 = o_perm1 + align_up(std::max<uint64_t>(n, 1) * pb, 256);
+    const size_t o_word1 = o_word0 + align_up(std::max<uint64_t>(n, 1) * 8, 256);
+    const size_t need = o_word1 + align_up(std::max<uint64_t>(n, 1) * 8, 256);
+    if (!workspace) {
+        *workspace_bytes = need;
+        return FS_OK;
+    }
+    if (n == 0) return FS_OK;
+    if (*workspace_bytes < need) return FS_ERR_WORKSPACE_TOO_SMALL;
+    if (!keys_in || !keys_out || (val_bytes && (!vals_in || !vals_out))) return FS_ERR_INVALID_ARG;
+    if (!aligned(keys_in, 8) || !aligned(keys_out, 8) || !aligned(workspace, 256)) return FS_ERR_INVALID_ARG;
+    if (val_bytes && (!aligned(vals_in, val_bytes) || !aligned(vals_out, val_bytes))) return FS_ERR_INVALID_ARG;
+    const uint64_t kbytes = n * 8ull * (uint64_t)words, vbytes = n * (uint64_t)val_bytes;
+    if (overlaps(keys_in, kbytes, keys_out, kbytes) || overlaps(workspace, need, keys_in, kbytes) ||
+        overlaps(workspace, need, keys_out, kbytes))
+        return FS_ERR_INVALID_ARG;
+    if (val_bytes && (overlaps(vals_in, vbytes, vals_out, vbytes) || overlaps(keys_in, kbytes, vals_in, vbytes) ||
+                      overlaps(keys_out, kbytes, vals_out, vbytes) || overlaps(keys_in, kbytes, vals_out, vbytes) ||
+                      overlaps(keys_out, kbytes, vals_in, vbytes) || overlaps(workspace, need, vals_in, vbytes) ||
+                      overlaps(workspace, need, vals_out, vbytes)))
+        return FS_ERR_INVALID_ARG;
+
+    char* w = static_cast<char*>(workspace);
+    void* perm[2] = {w + o_perm0, w + o_perm1};
+    uint64_t* word[2] = {reinterpret_cast<uint64_t*>(w + o_word0), reinterpret_cast<uint64_t*>(w + o_word1)};
+    int cur = 0;
+    for (int r = 0; r < words; ++r) {
+        uint64_t pos, neg;
+        word_masks(r, &pos, &neg);
+        FS_TRY(launch_gather_word(keys_in, (uint32_t)words, (uint32_t)r, r == 0 ? nullptr : perm[cur], pb, word[0],
+                                  n, pos, neg, s));
+        if (r == 0) FS_TRY(launch_iota(perm[cur], pb, n, s));
+        size_t ib = inner;
+        const fs_status st = sort_impl(word[0], word[1], perm[cur], perm[1 - cur], n, 64, pb, 0, w + o_inner, &ib, s);
+        if (st != FS_OK) return st;
+        cur = 1 - cur;
+    }
+    FS_TRY(launch_gather_keys(keys_in, keys_out, (uint32_t)words, perm[cur], pb, n, s));
+    if (val_bytes) FS_TRY(launch_gather_vals(vals_in, vals_out, val_bytes, perm[cur], pb, n, s));
+    return FS_OK;
+}
+
 }  // namespace fs
 
 extern "C" {
@@ -257,6 +346,20 @@ fs_status fs_sort_pairs(const void* keys_in, void* keys_out, const void* vals_in
     if (val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
     return fs::sort_impl(keys_in, keys_out, vals_in, vals_out, n, key_bits, val_bytes, flags, workspace,
                          workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+fs_status fs_sort_keys_wide(const void* keys_in, void* keys_out, uint64_t n, int key_words, unsigned flags,
+                            void* workspace, size_t* workspace_bytes, void* stream) {
+    return fs::sort_wide_impl(keys_in, keys_out, nullptr, nullptr, n, key_words, 0, flags, workspace,
+                              workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+fs_status fs_sort_pairs_wide(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out, uint64_t n,
+                             int key_words, int val_bytes, unsigned flags, void* workspace, size_t* workspace_bytes,
+                             void* stream) {
+    if (val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
+    return fs::sort_wide_impl(keys_in, keys_out, vals_in, vals_out, n, key_words, val_bytes, flags, workspace,
+                              workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 fs_status fs_digit_histograms(const void* keys, uint64_t n, int key_bits, int digit_bits,

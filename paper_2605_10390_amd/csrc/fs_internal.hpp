@@ -102,6 +102,18 @@ hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes,
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
                               uint32_t* wrap_word, hipStream_t s);
 
+// ---- multi-word keys (wide.hip) ---------------------------------------------
+// perm_bytes: 4 or 8 (width of a permutation entry)
+hipError_t launch_iota(void* perm, int perm_bytes, uint64_t n, hipStream_t s);
+// out[i] = word w of key perm[i] (key i when perm is null) ^ (pos, or neg when the
+// key's top word has its top bit set)
+hipError_t launch_gather_word(const void* keys, uint32_t words, uint32_t w, const void* perm, int perm_bytes,
+                              uint64_t* out, uint64_t n, uint64_t pos, uint64_t neg, hipStream_t s);
+hipError_t launch_gather_keys(const void* keys_in, void* keys_out, uint32_t words, const void* perm, int perm_bytes,
+                              uint64_t n, hipStream_t s);
+hipError_t launch_gather_vals(const void* vals_in, void* vals_out, int val_bytes, const void* perm, int perm_bytes,
+                              uint64_t n, hipStream_t s);
+
 // ---- per-kernel event timing (include/fs_profile.h) ------------------------
 void profile_mark(int kind, uint64_t keys, hipStream_t s, hipEvent_t* begin_out);
 void profile_close(int kind, uint64_t keys, hipStream_t s, hipEvent_t begin);

@@ -139,3 +139,39 @@ def test_planted_mistake_is_caught(monkeypatch, plant):
     assert _pins_pass()
     monkeypatch.setattr(oracle, "_order_columns", plant)
     assert not _pins_pass()
+
+
+# ---- keys of several 64-bit words -------------------------------------------------
+
+def test_wide_single_word_matches_ordered_sort():
+    rng = np.random.default_rng(41)
+    k = rng.integers(0, 1 << 63, size=3000, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, 3000).astype(np.uint64)
+    k[:500] = k[500:1000]
+    v = np.arange(k.size, dtype=np.uint32)
+    for key_type in ("unsigned", "signed", "float"):
+        for desc in (False, True):
+            wk, wv = oracle.sort_wide(k.reshape(-1, 1), v, key_type=key_type, descending=desc)
+            ek, ev = oracle.sort_ordered(k, v, key_type=key_type, descending=desc)
+            assert np.array_equal(wk.ravel(), ek) and np.array_equal(wv, ev), (key_type, desc)
+
+
+def test_wide_hand_ordered_two_word_keys():
+    top, allw = 1 << 63, (1 << 64) - 1
+    # (lo, hi) rows in unsigned order of the 128-bit value
+    rows = [(0, 0), (5, 0), (allw, 0), (0, 1), (3, 1), (0, top - 1), (0, top), (allw, allw)]
+    want = np.array(rows, dtype=np.uint64)
+    rng = np.random.default_rng(2)
+    shuffled = want[rng.permutation(len(rows))]
+    assert np.array_equal(oracle.sort_wide(shuffled), want)
+    # two's complement: keys with the top bit set are negative, most negative first
+    signed = [want[6], want[7], *want[:6]]
+    assert np.array_equal(oracle.sort_wide(shuffled, key_type="signed"), np.array(signed))
+    # binary128: -NaN, -inf, -1, -0, +0, 1, +inf, +NaN (hi word holds sign, exponent, top fraction)
+    f128 = [(1, 0xFFFF800000000000), (0, 0xFFFF000000000000), (0, 0xBFFF000000000000),
+            (0, 0x8000000000000000), (0, 0), (0, 0x3FFF000000000000), (0, 0x7FFF000000000000),
+            (1, 0x7FFF800000000000)]
+    f = np.array(f128, dtype=np.uint64)
+    for _ in range(5):
+        sh = f[rng.permutation(len(f128))]
+        assert np.array_equal(oracle.sort_wide(sh, key_type="float"), f)
+        assert np.array_equal(oracle.sort_wide(sh, key_type="float", descending=True), f[::-1])

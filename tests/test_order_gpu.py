@@ -117,3 +117,28 @@ def test_segmented_in_every_order(gpu, key_type, desc):
         else:
             assert np.array_equal(host(ko), w[0]), SEGMENTS[i]
             assert np.array_equal(host(vo), w[1]), SEGMENTS[i]
+
+
+@pytest.mark.parametrize("words", [1, 2, 3])
+@pytest.mark.parametrize("key_type", ["unsigned", "signed", "float"])
+def test_wide_keys_match_oracle(gpu, words, key_type):
+    """Keys of several 64-bit words, against the oracle's whole-width
+    integer comparison; repeated keys and keys equal in their low words
+    check stability and the word order."""
+    rng = np.random.default_rng(17 * words)
+    ws = fs.Workspace(gpu)
+    for n in (1, 1000, 70_001):
+        k = rng.integers(0, 1 << 63, size=(n, words), dtype=np.uint64) * np.uint64(2)
+        k += rng.integers(0, 2, size=(n, words)).astype(np.uint64)
+        if n > 10:
+            k[: n // 4] = k[n // 4: n // 2]          # whole-key repeats
+            k[n // 2: n // 2 + n // 8, 1:] = k[0, 1:]  # equal high words, differing low words
+            k[-n // 8:, :-1] = 7                      # equal low words, differing high words
+        v = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+        for desc in (False, True):
+            got = fs.sort_wide(dev(k), workspace=ws, key_type=key_type, descending=desc)
+            assert np.array_equal(host(got), oracle.sort_wide(k, key_type=key_type, descending=desc)), (n, desc)
+            gk, gv = fs.sort_wide(dev(k), dev(v), workspace=ws, key_type=key_type, descending=desc)
+            ek, ev = oracle.sort_wide(k, v, key_type=key_type, descending=desc)
+            assert ws.error_word() == 0
+            assert np.array_equal(host(gk), ek) and np.array_equal(host(gv), ev), (n, desc)
