@@ -68,7 +68,8 @@ typedef enum {
  *                       and the sign of zero survive.
  *   FS_FLAG_DESCENDING  largest key first.  Stability is kept: equal keys
  *                       (same bits) stay in input order.
- * SIGNED and FLOAT exclude each other; any other bit is FS_ERR_INVALID_ARG.
+ * SIGNED and FLOAT exclude each other, FLOAT needs 16 bits or more; any
+ * other bit is FS_ERR_INVALID_ARG.
  * fs_sort_segmented applies the flags to every segment of the call.
  */
 enum {
@@ -82,7 +83,7 @@ enum {
  * Stable ascending sort of n unsigned keys (Section II phases; for 16-bit
  * keys the whole sort is the compressed 2^16-bin histogram written out in
  * order, Algorithm 5 with no trailing bits).
- *   keys_in   device, n keys of key_bits bits (16, 32 or 64); not modified.
+ *   keys_in   device, n keys of key_bits bits (8, 16, 32 or 64); not modified.
  *   keys_out  device, n keys; must not overlap keys_in.
  *   flags     key order (FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING).
  */
@@ -94,7 +95,7 @@ fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_
  * ascending order and vals_out[i] is the value that came with keys_out[i];
  * equal keys keep their input order.  With vals_in[i] = i, vals_out is the
  * paper's index array (sorted position -> arrival position, Section III-G.3).
- *   keys_in/keys_out  device, n keys of key_bits bits (16, 32, 64).
+ *   keys_in/keys_out  device, n keys of key_bits bits (8, 16, 32, 64).
  *   vals_in/vals_out  device, n values of val_bytes bytes (4 or 8).
  * None of the four ranges may overlap another.  flags: key order, as for
  * fs_sort_keys.

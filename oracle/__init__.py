@@ -161,7 +161,7 @@ def sort_segments(segments, lib=None):
     return out
 
 
-_SIGNED = {2: np.int16, 4: np.int32, 8: np.int64}
+_SIGNED = {1: np.int8, 2: np.int16, 4: np.int32, 8: np.int64}
 _FLOAT = {2: np.float16, 4: np.float32, 8: np.float64}
 
 

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libfsort.so")
 
 FS_OK, FS_ERR_INVALID_ARG, FS_ERR_UNSUPPORTED, FS_ERR_WORKSPACE_TOO_SMALL, FS_ERR_DEVICE = range(5)
 
-_KEY_BITS = {torch.uint16: 16, torch.int16: 16, torch.uint32: 32, torch.int32: 32,
+_KEY_BITS = {torch.uint8: 8, torch.int8: 8, torch.uint16: 16, torch.int16: 16, torch.uint32: 32, torch.int32: 32,
              torch.uint64: 64, torch.int64: 64, torch.float16: 16, torch.bfloat16: 16,
              torch.float32: 32, torch.float64: 64}
 FS_FLAG_NONE, FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING = 0, 1, 2, 4
@@ -112,7 +112,7 @@ def _key_bits(keys):
 def order_flags(keys, key_type=None, descending=False):
     """fs_sort flags for a key tensor: key_type None follows the dtype."""
     if key_type is None:
-        if keys.dtype in (torch.int16, torch.int32, torch.int64):
+        if keys.dtype in (torch.int8, torch.int16, torch.int32, torch.int64):
             key_type = "signed"
         elif keys.dtype.is_floating_point:
             key_type = "float"

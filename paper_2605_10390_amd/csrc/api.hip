@@ -51,11 +51,12 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
         L.tile_blocks = ceil_div(L.tiles, 65536 / L.tile);
         L.tile_supers = ceil_div(L.tile_blocks, kSuperBlock);
         L.hist_groups = (uint32_t)std::min<uint64_t>(L.tile_blocks, 4ull * num_cus);
-        static const int per_cu[3][3] = {
+        static const int per_cu[4][3] = {
+            {tiled_scatter_per_cu(1, 0), tiled_scatter_per_cu(1, 4), tiled_scatter_per_cu(1, 8)},
             {0, tiled_scatter_per_cu(2, 4), tiled_scatter_per_cu(2, 8)},
             {tiled_scatter_per_cu(4, 0), tiled_scatter_per_cu(4, 4), tiled_scatter_per_cu(4, 8)},
             {tiled_scatter_per_cu(8, 0), tiled_scatter_per_cu(8, 4), tiled_scatter_per_cu(8, 8)}};
-        const int ki = key_bytes == 2 ? 0 : key_bytes == 4 ? 1 : 2, vi = val_bytes / 4;
+        const int ki = key_bytes == 1 ? 0 : key_bytes == 2 ? 1 : key_bytes == 4 ? 2 : 3, vi = val_bytes / 4;
         L.scatter_groups = (uint32_t)std::max(1, num_cus * std::max(1, per_cu[ki][vi]));
         L.part = take(4ull * L.hist_groups * L.digits * kRadix);
         L.th = take(2ull * kRadix * L.tiles);
@@ -103,6 +104,7 @@ constexpr uint64_t kMaxKeys = 1ull << 36;
 static bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* neg) {
     const unsigned known = FS_FLAG_SIGNED | FS_FLAG_FLOAT | FS_FLAG_DESCENDING;
     if ((flags & ~known) || ((flags & FS_FLAG_SIGNED) && (flags & FS_FLAG_FLOAT))) return false;
+    if ((flags & FS_FLAG_FLOAT) && key_bits == 8) return false;  // no 8-bit IEEE format
     const uint64_t all = key_bits == 64 ? ~0ull : (1ull << key_bits) - 1;
     const uint64_t sign = 1ull << (key_bits - 1);
     uint64_t p = 0, q = 0;
@@ -123,7 +125,7 @@ static bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* n
 static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,
                            uint64_t n, int key_bits, int val_bytes, unsigned flags, void* workspace,
                            size_t* workspace_bytes, hipStream_t s) {
-    if (key_bits != 16 && key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
+    if (key_bits != 8 && key_bits != 16 && key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
     uint64_t opos = 0, oneg = 0;
     if (!order_masks(flags, key_bits, &opos, &oneg)) return FS_ERR_INVALID_ARG;
     if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;

@@ -451,7 +451,8 @@ hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint
     auto grid = [](uint64_t words) { uint64_t g = (words + 255) / 256; return (unsigned)(g > 8192 ? 8192 : g); };
     if ((m & 15) == 0) k_copy_if<uint4><<<grid(bytes / 16), 256, 0, s>>>(plan, (const uint4*)src, (uint4*)dst, bytes / 16);
     else if ((m & 3) == 0) k_copy_if<uint32_t><<<grid(bytes / 4), 256, 0, s>>>(plan, (const uint32_t*)src, (uint32_t*)dst, bytes / 4);
-    else k_copy_if<uint16_t><<<grid(bytes / 2), 256, 0, s>>>(plan, (const uint16_t*)src, (uint16_t*)dst, bytes / 2);
+    else if ((m & 1) == 0) k_copy_if<uint16_t><<<grid(bytes / 2), 256, 0, s>>>(plan, (const uint16_t*)src, (uint16_t*)dst, bytes / 2);
+    else k_copy_if<uint8_t><<<grid(bytes), 256, 0, s>>>(plan, (const uint8_t*)src, (uint8_t*)dst, bytes);
     return hipGetLastError();
 }
 

@@ -732,6 +732,9 @@ void k_tile_scatter(TiledArgs a, int pass) {
 // Tile shapes and launchers
 // ---------------------------------------------------------------------------
 #define FS_TILED_SHAPES(X)                 \
+    X(uint8_t, NoVal, 512, 8, false)       \
+    X(uint8_t, uint32_t, 512, 8, false)    \
+    X(uint8_t, uint64_t, 512, 8, false)    \
     X(uint16_t, uint32_t, 512, 8, false)   \
     X(uint16_t, uint64_t, 512, 8, false)   \
     X(uint32_t, NoVal, 512, 8, false)      \
@@ -779,7 +782,8 @@ static void launch_hist_t(const TiledArgs& a, int pass, uint32_t groups, hipStre
 }
 
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
-    if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, groups, s);
+    if (key_bytes == 1 && a.tile == 4096) launch_hist_t<uint8_t, 4096>(a, pass, groups, s);
+    else if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, groups, s);
     else if (key_bytes == 2 && a.tile == 8192) launch_hist_t<uint16_t, 8192>(a, pass, groups, s);
     else if (key_bytes == 2 && a.tile == 16384) launch_hist_t<uint16_t, 16384>(a, pass, groups, s);
     else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, groups, s);

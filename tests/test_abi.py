@@ -50,3 +50,7 @@ def test_argument_errors_need_no_gpu():
     assert lib.fs_sort_keys(None, None, 10, 16, 8, None, ctypes.byref(size), None) == 1
     for flags in (1, 2, 4, 5, 6):
         assert lib.fs_sort_keys(None, None, 10, 32, flags, None, ctypes.byref(size), None) == 0
+    # 8-bit keys take every order but FLOAT
+    for flags in (0, 1, 4, 5):
+        assert lib.fs_sort_keys(None, None, 10, 8, flags, None, ctypes.byref(size), None) == 0
+    assert lib.fs_sort_keys(None, None, 10, 8, 2, None, ctypes.byref(size), None) == 1

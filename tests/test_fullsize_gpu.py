@@ -87,7 +87,9 @@ def counts16(t, shift):
         c = as_i64(t[a:a + CHUNK])
         if t.dtype == torch.uint64:
             c = c ^ I64_MIN  # back to the raw bits
-        out += torch.bincount((c >> shift) & 0xFFFF, minlength=65536)
+        # sort-based counting: no atomic contention when few values dominate
+        vals, cnt = torch.unique((c >> shift) & 0xFFFF, return_counts=True)
+        out.index_add_(0, vals, cnt)
     return out
 
 

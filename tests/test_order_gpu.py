@@ -142,3 +142,29 @@ def test_wide_keys_match_oracle(gpu, words, key_type):
             ek, ev = oracle.sort_wide(k, v, key_type=key_type, descending=desc)
             assert ws.error_word() == 0
             assert np.array_equal(host(gk), ek) and np.array_equal(host(gv), ev), (n, desc)
+
+
+@pytest.mark.parametrize("key_type,desc", [("unsigned", False), ("unsigned", True), ("signed", False),
+                                           ("signed", True)])
+def test_8bit_keys_and_pairs(gpu, key_type, desc):
+    """8-bit keys (one digit): keys only and with 4- and 8-byte payloads,
+    across tile boundaries with ragged tails, unaligned starts, skewed and
+    all-equal keys."""
+    rng = np.random.default_rng(8)
+    ws = fs.Workspace(gpu)
+    for n in (1, 15, 17, 4095, 4097, 3 * 4096 + 5, 65536 + 7, (1 << 20) + 3):
+        k = rng.integers(0, 256, n, dtype=np.uint64).astype(np.uint8)
+        if n > 100:
+            k[: n // 3] = 200  # a hot value
+        for off in (0, 3):
+            kk = dev(np.concatenate([np.zeros(off, np.uint8), k]))[off:]
+            got = fs.sort_keys(kk, workspace=ws, key_type=key_type, descending=desc)
+            assert np.array_equal(host(got), oracle.sort_ordered(k, key_type=key_type, descending=desc)), (n, off)
+        for vdt in (np.uint32, np.uint64):
+            v = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(vdt)
+            gk, gv = fs.sort_pairs(dev(k), dev(v), workspace=ws, key_type=key_type, descending=desc)
+            ek, ev = oracle.sort_ordered(k, v, key_type=key_type, descending=desc)
+            assert ws.error_word() == 0
+            assert np.array_equal(host(gk), ek) and np.array_equal(host(gv), ev), (n, vdt)
+    eq = np.full(70_000, 9, np.uint8)
+    assert np.array_equal(host(fs.sort_keys(dev(eq), key_type=key_type, descending=desc)), eq)
