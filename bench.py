@@ -408,6 +408,55 @@ def run_stream16(args):
     print(json.dumps(res), flush=True)
 
 
+def run_host32(args):
+    """Out-of-core sort of 32-bit keys (fs_sort_host): 2^31 uint32 keys
+    (8 GiB) in pinned host memory, with device ranges of at most 2^29 keys,
+    so the sort spills through four or more ranges as if the keys did not fit
+    the device.  The input crosses the host link (ranges + 2) times and the
+    output once; the bound is the link's per-direction rate."""
+    import torch
+    import fsgen
+    import paper_2605_10390_amd as fs
+    dev = torch.device("cuda:0")
+    n, batch, dk = 1 << 31, 1 << 26, 1 << 29
+    seed = fsgen.seed_for(2, 0)
+    src = torch.empty(n, dtype=torch.uint32, pin_memory=True)
+    src.copy_(fsgen.keys_device("uniform", 32, n, seed, device=dev))
+    out = torch.empty(n, dtype=torch.uint32, pin_memory=True)
+    ws = fs.Workspace(dev)
+    xs = torch.cuda.Stream(dev)
+    for _ in range(args.warmup):
+        fs.sort_host(src, out=out, batch_keys=batch, device_keys=dk, workspace=ws, copy_stream=xs, device=dev)
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fs.sort_host(src, out=out, batch_keys=batch, device_keys=dk, workspace=ws, copy_stream=xs, device=dev)
+        times.append(time.perf_counter() - t0)
+    ms = 1e3 * sum(times) / len(times)
+    o = out.view(torch.int32)
+    for a in range(0, n, 1 << 28):  # cheap validity check outside the timed region
+        c = o[a:a + (1 << 28)].to(torch.int64) & 0xFFFFFFFF
+        assert bool((c[1:] >= c[:-1]).all()), "output not sorted"
+    ranges = -(-n // dk)  # at least; uniform keys fill ranges nearly to the bound
+    link_bytes = 4 * n * (ranges + 2) + 4 * n
+    achieved = link_bytes / (ms / 1e3) / 1e9
+    res = {"metric": "Gkeys/s, 32-bit keys sorted host to host through the device (out-of-core MSD spill)",
+           "value": round(n / (ms / 1e3) / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "out-of-core sort of 2^31 uint32 keys (8 GiB) in pinned host memory, device "
+                                  "ranges of at most 2^29 keys, 2^26-key batches, uniform", "n": n,
+                      "batch_keys": batch, "device_keys": dk, "seed": seed,
+                      "parallelism": "single GPU, copy stream + compute stream"},
+           "roofline": {"bound": "pcie", "kernel": None, "achieved": round(achieved, 2), "peak": PCIE5_X16_GBPS,
+                        "unit": "GB/s", "frac": round(achieved / PCIE5_X16_GBPS, 4), "traffic": None,
+                        "bytes_per_key": 4 * (ranges + 3)}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(src, None, 32, 0)
+    print(json.dumps(res), flush=True)
+
+
 def pmc_summary(fetch_csv, write_csv, kernel, out_path, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
     dispatch) of `bench.py --copy-probe` into HBM bytes per launch of
@@ -445,7 +494,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4", "stream16"])
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4", "stream16", "host32"])
     ap.add_argument("--jobs", type=int, default=1000, help="served-stream prefix length (c4)")
     ap.add_argument("--dist", default=None,
                     help="c0/c1/c2a/c2b: key distribution (16-bit: uniform gaussian zipf equal presorted "
@@ -475,6 +524,8 @@ def main():
         return run_c4(args)
     if args.workload == "stream16":
         return run_stream16(args)
+    if args.workload == "host32":
+        return run_host32(args)
 
     import torch
     import ctypes

@@ -305,6 +305,31 @@ fs_status fs_sort16_host(const void *h_keys_in, void *h_keys_out, uint64_t n, ui
                          void *workspace, size_t *workspace_bytes, void *copy_stream,
                          void *compute_stream);
 
+/*
+ * fs_sort_host: ascending sort of n 32- or 64-bit keys (key_bits) that live
+ *   in HOST memory and need not fit in device memory (batch stream sorting,
+ *   Section I contribution 2, for keys whose histogram is not the whole
+ *   multiset).  An MSD spill over the host input, streamed through two
+ *   staging slots of batch_keys keys:
+ *     1. one read finds the bits on which keys differ;
+ *     2. one read builds the compressed 2^16-bin histogram (Section III-B)
+ *        of the 16 bits just below the highest such bit;
+ *     3. consecutive bins are grouped into ranges of at most device_keys
+ *        keys, in key order; for each range one more read gathers its keys
+ *        on the device, fs_sort_keys sorts them, and they are copied to
+ *        their place in h_keys_out.
+ *   The input is read (number of ranges + 2) times.  h_keys_in/h_keys_out:
+ *   host, n keys, not overlapping (the input is read until the last range);
+ *   pinned memory (hipHostMalloc) makes the copies asynchronous.  When every
+ *   key is equal the input is copied.  FS_ERR_UNSUPPORTED when one bin of
+ *   the histogram holds more than device_keys keys.  The workspace size
+ *   depends on batch_keys and device_keys.  Blocks until h_keys_out holds
+ *   the result.  n == 0 is FS_OK and a no-op.
+ */
+fs_status fs_sort_host(const void *h_keys_in, void *h_keys_out, uint64_t n, int key_bits, uint64_t batch_keys,
+                       uint64_t device_keys, void *workspace, size_t *workspace_bytes, void *copy_stream,
+                       void *compute_stream);
+
 const char *fs_status_string(fs_status s);
 
 #ifdef __cplusplus

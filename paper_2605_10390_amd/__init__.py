@@ -81,6 +81,8 @@ def lib():
     L.fs_expand16.restype = i32
     L.fs_sort16_host.argtypes = [vp, vp, u64, u64, vp, sz, vp, vp]
     L.fs_sort16_host.restype = i32
+    L.fs_sort_host.argtypes = [vp, vp, u64, i32, u64, u64, vp, sz, vp, vp]
+    L.fs_sort_host.restype = i32
     L.fs_status_string.argtypes = [i32]
     L.fs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -541,4 +543,36 @@ def sort16_host(keys, out=None, batch_keys=1 << 26, workspace=None, copy_stream=
                               ctypes.c_void_p(cs.cuda_stream))
     if st != FS_OK:
         raise FsError(st, "fs_sort16_host")
+    return out
+
+
+def sort_host(keys, out=None, batch_keys=1 << 26, device_keys=1 << 30, workspace=None, copy_stream=None,
+              device="cuda"):
+    """Sort 32- or 64-bit keys held in HOST memory (a CPU tensor, ideally
+    pinned) that need not fit on the device: an MSD spill through ranges of
+    at most `device_keys` keys.  Blocks until `out` holds the result."""
+    if keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("sort_host takes a contiguous host tensor")
+    bits = _key_bits(keys)
+    if bits not in (32, 64):
+        raise TypeError("sort_host takes 32- or 64-bit keys (16-bit keys: sort16_host)")
+    out = torch.empty(keys.shape, dtype=keys.dtype, pin_memory=keys.is_pinned()) if out is None else out
+    if out.is_cuda or out.numel() != keys.numel() or out.dtype != keys.dtype:
+        raise ValueError("out must be a host tensor like keys")
+    dev = torch.device(device)
+    L = lib()
+    size = ctypes.c_size_t(0)
+    st = L.fs_sort_host(None, None, 0, bits, int(batch_keys), int(device_keys), None, ctypes.byref(size), None,
+                        None)
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_host (workspace query)")
+    ws = workspace or Workspace(dev)
+    buf = ws.get(size.value)
+    size = ctypes.c_size_t(buf.numel())
+    xs = copy_stream if copy_stream is not None else torch.cuda.Stream(dev)
+    cs = torch.cuda.current_stream(dev)
+    st = L.fs_sort_host(_ptr(keys), _ptr(out), keys.numel(), bits, int(batch_keys), int(device_keys), _ptr(buf),
+                        ctypes.byref(size), ctypes.c_void_p(xs.cuda_stream), ctypes.c_void_p(cs.cuda_stream))
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_host")
     return out

@@ -1,5 +1,5 @@
-// Batch stream sorting of 16-bit keys (include/fs_sort.h, fs_hist16_* /
-// fs_expand16 / fs_sort16_host).  Host code only.
+// Batch stream sorting (include/fs_sort.h): fs_hist16_* / fs_expand16 /
+// fs_sort16_host for 16-bit keys, fs_sort_host for 32- and 64-bit keys.
 //
 // For 16-bit keys the 2^16-bin histogram is the whole multiset, so a stream
 // of batches is sorted by adding each batch's compressed histogram into one
@@ -14,6 +14,8 @@
 #include "fs_internal.hpp"
 
 #include <algorithm>
+#include <cstring>
+#include <vector>
 
 namespace fs {
 namespace {
@@ -182,6 +184,288 @@ fs_status fs_sort16_host(const void* h_keys_in, void* h_keys_out, uint64_t n, ui
     // the host output is complete only when both streams have drained
     const bool drained = hipStreamSynchronize(xs) == hipSuccess && hipStreamSynchronize(cs) == hipSuccess;
     return ok && drained ? FS_OK : FS_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Out-of-core sort of 32- and 64-bit keys (fs_sort_host): an MSD spill.  The
+// 16 bits just below the highest bit on which keys differ split the key
+// range into 2^16 ordered buckets; consecutive buckets are grouped into
+// ranges that fit the device, and each range is gathered from the streamed
+// input, sorted on the device and written to its place in the output.
+// ---------------------------------------------------------------------------
+namespace fs {
+namespace {
+
+constexpr int kHostThreads = 256;
+
+// OR and AND of every key (the bits on which keys differ are OR ^ AND)
+template <typename K>
+__global__ __launch_bounds__(kHostThreads) void k_or_and(const K* __restrict__ keys, uint64_t n,
+                                                         unsigned long long* acc) {
+    uint64_t o = 0, a = ~0ull;
+    const uint64_t stride = (uint64_t)gridDim.x * kHostThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kHostThreads + threadIdx.x; i < n; i += stride) {
+        o |= (uint64_t)keys[i];
+        a &= (uint64_t)keys[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        o |= __shfl_xor(o, off, 64);
+        a &= __shfl_xor(a, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicOr(&acc[0], (unsigned long long)o);
+        atomicAnd(&acc[1], (unsigned long long)a);
+    }
+}
+
+// compressed 2^16-bin histogram (hist16_add) of bits [shift, shift + 16) of the keys
+template <typename K>
+__global__ __launch_bounds__(kHostThreads) void k_hist_window(const K* __restrict__ keys, uint64_t n, int shift,
+                                                              uint32_t* __restrict__ part, uint32_t* wrap_lo,
+                                                              uint32_t* wrap_word) {
+    __shared__ uint32_t cnt[kHist16Words];
+    for (int i = threadIdx.x; i < kHist16Words; i += kHostThreads) cnt[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * kHostThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kHostThreads + threadIdx.x; i < n; i += stride)
+        hist16_add(cnt, (uint32_t)(((uint64_t)keys[i] >> shift) & 0xFFFFu), 1u, wrap_lo, wrap_word);
+    __syncthreads();
+    uint32_t* dst = part + (uint64_t)blockIdx.x * kHist16Words;
+    for (int i = threadIdx.x; i < kHist16Words; i += kHostThreads) dst[i] = cnt[i];
+}
+
+// append the keys whose window value lies in [lo, hi) to out (order within a
+// range does not matter: equal keys are equal bits).  Each block counts the
+// matches of its contiguous chunk, reserves that many slots with one atomic,
+// then writes them (a second read of the chunk, from device memory).
+template <typename K>
+__global__ __launch_bounds__(kHostThreads) void k_select_range(const K* __restrict__ keys, uint64_t n, int shift,
+                                                               uint32_t lo, uint32_t hi, K* __restrict__ out,
+                                                               uint64_t cap, unsigned long long* count,
+                                                               uint32_t* err) {
+    __shared__ unsigned long long s_base;
+    __shared__ uint32_t s_cnt;
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t c0 = (uint64_t)blockIdx.x * per, c1 = c0 + per < n ? c0 + per : n;
+    auto in_range = [&](K k) {
+        const uint32_t v = (uint32_t)(((uint64_t)k >> shift) & 0xFFFFu);
+        return v >= lo && v < hi;
+    };
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kHostThreads) mine += in_range(keys[i]) ? 1u : 0u;
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&s_cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_base = s_cnt ? atomicAdd(count, (unsigned long long)s_cnt) : 0ull;
+        s_cnt = 0;
+    }
+    __syncthreads();
+    const unsigned long long base = s_base;
+    for (uint64_t i0 = c0; i0 < c1; i0 += kHostThreads) {
+        const uint64_t i = i0 + threadIdx.x;
+        const K k = i < c1 ? keys[i] : (K)0;
+        const bool take = i < c1 && in_range(k);
+        const uint64_t m = ballot(take);
+        if (m == 0) continue;
+        uint32_t wbase = 0;
+        if (lanes_below(m) == 0 && take) wbase = atomicAdd(&s_cnt, (uint32_t)popc64(m));
+        wbase = __shfl(wbase, __builtin_ctzll(m), 64);
+        if (take) {
+            const uint64_t j = base + wbase + lanes_below(m);
+            if (j < cap) out[j] = k;
+            else atomicOr(err, 128u);  // more keys than the histogram counted
+        }
+    }
+}
+
+uint32_t host_grid(uint64_t n) {
+    const uint64_t g = (n + kHostThreads - 1) / kHostThreads;
+    const uint64_t cap = 4ull * (uint64_t)device_cu_count();
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, cap));
+}
+
+}  // namespace
+}  // namespace fs
+
+extern "C" {
+
+fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int key_bits, uint64_t batch_keys,
+                       uint64_t device_keys, void* workspace, size_t* workspace_bytes, void* copy_stream,
+                       void* compute_stream) {
+    using namespace fs;
+    if (key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
+    if (!workspace_bytes || n > kMaxStreamKeys || batch_keys == 0 || batch_keys > kMaxStreamKeys ||
+        device_keys == 0 || device_keys > kMaxStreamKeys)
+        return FS_ERR_INVALID_ARG;
+    const int kb = key_bits / 8;
+    const uint64_t batch = (batch_keys + 3) / 4 * 4;
+    size_t inner = 0;
+    if (fs_sort_keys(nullptr, nullptr, device_keys, key_bits, 0, nullptr, &inner, nullptr) != FS_OK)
+        return FS_ERR_INVALID_ARG;
+    const uint32_t groups = host_grid(batch);
+    // layout: inner sort workspace first (word 0 is its error word), then
+    // the histogram, the reductions, the histogram parts, the staging slots,
+    // the range buffer and its sorted copy
+    const size_t o_inner = 0;
+    const size_t o_hist = align256(inner);
+    const size_t o_acc = o_hist + align256(kHistBytes);
+    const size_t o_part = o_acc + 256;
+    const size_t o_wrap = o_part + align256(4ull * groups * kHist16Words);
+    const size_t o_slot0 = o_wrap + align256(4ull * 2 * kHist16Words);
+    const size_t slot = align256(batch * kb);
+    const size_t o_range = o_slot0 + 2 * slot;
+    const size_t o_sorted = o_range + align256(device_keys * kb);
+    const size_t need = o_sorted + align256(device_keys * kb);
+    if (!workspace) {
+        *workspace_bytes = need;
+        return FS_OK;
+    }
+    if (*workspace_bytes < need) return FS_ERR_WORKSPACE_TOO_SMALL;
+    if ((n && (!h_keys_in || !h_keys_out)) || !aligned(workspace, 256) || (h_keys_in && !aligned(h_keys_in, kb)) ||
+        (h_keys_out && !aligned(h_keys_out, kb)))
+        return FS_ERR_INVALID_ARG;
+    const uintptr_t ia = reinterpret_cast<uintptr_t>(h_keys_in), oa = reinterpret_cast<uintptr_t>(h_keys_out);
+    if (n && ia < oa + n * kb && oa < ia + n * kb) return FS_ERR_INVALID_ARG;  // the input is read to the end
+    if (n == 0) return FS_OK;
+
+    hipStream_t cs = static_cast<hipStream_t>(compute_stream);
+    hipStream_t xs = static_cast<hipStream_t>(copy_stream);
+    char* ws = static_cast<char*>(workspace);
+    uint32_t* err = reinterpret_cast<uint32_t*>(ws + o_inner);
+    uint64_t* hist = reinterpret_cast<uint64_t*>(ws + o_hist);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws + o_acc);  // or, and, count
+    uint32_t* serr = reinterpret_cast<uint32_t*>(acc + 3);  // selection's error word
+    uint32_t* part = reinterpret_cast<uint32_t*>(ws + o_part);
+    uint32_t* wrap = reinterpret_cast<uint32_t*>(ws + o_wrap);
+    char* slots[2] = {ws + o_slot0, ws + o_slot0 + slot};
+    char* range = ws + o_range;
+    char* sorted = ws + o_sorted;
+    const char* in = static_cast<const char*>(h_keys_in);
+    char* out = static_cast<char*>(h_keys_out);
+    const uint64_t batches = (n + batch - 1) / batch;
+
+    SlotEvents ev;
+    if (!ev.ok) return FS_ERR_DEVICE;
+    // copies back to the host run on a stream of their own (default
+    // priority), beside the next range's copies in
+    struct OwnStream {
+        hipStream_t s = nullptr;
+        hipEvent_t sorted = nullptr, drained = nullptr;
+        bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&sorted, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&drained, hipEventDisableTiming) == hipSuccess;
+        ~OwnStream() {
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+            if (sorted) (void)hipEventDestroy(sorted);
+            if (drained) (void)hipEventDestroy(drained);
+        }
+    } back;
+    if (!back.ok) return FS_ERR_DEVICE;
+    bool ok = launch_fill_u32(err, 1, 0u, cs) == hipSuccess;
+    // stream every batch through the two staging slots, running `work` on
+    // each as it arrives (compute stream), then wait for the compute stream
+    auto stream_input = [&](auto&& work) {
+        for (uint64_t b = 0; ok && b < batches; ++b) {
+            const int i = (int)(b & 1);
+            const uint64_t off = b * batch, len = std::min(batch, n - off);
+            if (b >= 2) ok = hipStreamWaitEvent(xs, ev.emptied[i], 0) == hipSuccess;
+            ok = ok && hipMemcpyAsync(slots[i], in + off * kb, len * kb, hipMemcpyHostToDevice, xs) == hipSuccess;
+            ok = ok && hipEventRecord(ev.filled[i], xs) == hipSuccess;
+            ok = ok && hipStreamWaitEvent(cs, ev.filled[i], 0) == hipSuccess;
+            ok = ok && work(slots[i], len);
+            ok = ok && hipEventRecord(ev.emptied[i], cs) == hipSuccess;
+        }
+        ok = ok && hipStreamSynchronize(cs) == hipSuccess;
+    };
+    auto launch_ok = [&]() { return hipGetLastError() == hipSuccess; };
+
+    // 1. the bits on which keys differ
+    ok = ok && launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 2, 0u, cs) == hipSuccess &&
+         launch_fill_u32(reinterpret_cast<uint32_t*>(acc + 1), 2, 0xFFFFFFFFu, cs) == hipSuccess &&
+         launch_fill_u32(serr, 1, 0u, cs) == hipSuccess;
+    stream_input([&](const char* keys, uint64_t len) {
+        if (kb == 4) k_or_and<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>((const uint32_t*)keys, len, acc);
+        else k_or_and<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>((const uint64_t*)keys, len, acc);
+        return launch_ok();
+    });
+    unsigned long long oa_h[2] = {0, 0};
+    ok = ok && hipMemcpy(oa_h, acc, sizeof oa_h, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) return FS_ERR_DEVICE;
+    const uint64_t diff = oa_h[0] ^ oa_h[1];
+    if (diff == 0) {  // every key is the same: the input is sorted
+        std::memcpy(out, in, n * kb);
+        return FS_OK;
+    }
+    const int top = 63 - __builtin_clzll(diff);
+    const int shift = top >= 15 ? top - 15 : 0;
+
+    // 2. 2^16-bin histogram of the window [shift, shift + 16)
+    ok = launch_fill_u32(reinterpret_cast<uint32_t*>(hist), 2 * 65536, 0, cs) == hipSuccess;
+    stream_input([&](const char* keys, uint64_t len) {
+        const uint32_t g = std::min<uint32_t>(groups, host_grid(len));
+        if (launch_fill_u32(wrap, 2ull * kHist16Words, 0, cs) != hipSuccess) return false;
+        if (kb == 4)
+            k_hist_window<uint32_t><<<g, kHostThreads, 0, cs>>>((const uint32_t*)keys, len, shift, part, wrap,
+                                                                wrap + kHist16Words);
+        else
+            k_hist_window<uint64_t><<<g, kHostThreads, 0, cs>>>((const uint64_t*)keys, len, shift, part, wrap,
+                                                                wrap + kHist16Words);
+        return launch_ok() && launch_merge16(part, g, wrap, wrap + kHist16Words, hist, cs, true) == hipSuccess;
+    });
+    std::vector<uint64_t> h(65536);
+    ok = ok && hipMemcpy(h.data(), hist, kHistBytes, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) return FS_ERR_DEVICE;
+
+    // 3. ranges of consecutive window values that fit the device, in order
+    uint64_t placed = 0;
+    for (uint32_t v0 = 0; v0 < 65536;) {
+        uint64_t cnt = 0;
+        uint32_t v1 = v0;
+        while (v1 < 65536 && cnt + h[v1] <= device_keys) cnt += h[v1++];
+        if (v1 == v0) return FS_ERR_UNSUPPORTED;  // one window value holds more keys than the device takes
+        if (cnt) {
+            ok = launch_fill_u32(reinterpret_cast<uint32_t*>(acc + 2), 2, 0u, cs) == hipSuccess;
+            stream_input([&](const char* keys, uint64_t len) {
+                if (kb == 4)
+                    k_select_range<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>(
+                        (const uint32_t*)keys, len, shift, v0, v1, (uint32_t*)range, cnt, acc + 2, serr);
+                else
+                    k_select_range<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>(
+                        (const uint64_t*)keys, len, shift, v0, v1, (uint64_t*)range, cnt, acc + 2, serr);
+                return launch_ok();
+            });
+            unsigned long long got = 0;
+            ok = ok && hipMemcpy(&got, acc + 2, sizeof got, hipMemcpyDeviceToHost) == hipSuccess;
+            if (!ok || got != cnt) return FS_ERR_DEVICE;
+            // the previous range's copy back must have left the sorted buffer
+            ok = hipStreamWaitEvent(cs, back.drained, 0) == hipSuccess;
+            size_t ib = inner;
+            if (!ok || fs_sort_keys(range, sorted, cnt, key_bits, 0, ws + o_inner, &ib, cs) != FS_OK)
+                return FS_ERR_DEVICE;
+            uint32_t e = 0;  // the range sort's error word
+            ok = hipEventRecord(back.sorted, cs) == hipSuccess &&
+                 hipStreamWaitEvent(back.s, back.sorted, 0) == hipSuccess &&
+                 hipMemcpyAsync(out + placed * kb, sorted, cnt * kb, hipMemcpyDeviceToHost, back.s) == hipSuccess &&
+                 hipEventRecord(back.drained, back.s) == hipSuccess &&
+                 hipStreamSynchronize(cs) == hipSuccess &&
+                 hipMemcpy(&e, err, sizeof e, hipMemcpyDeviceToHost) == hipSuccess;
+            if (!ok || e != 0) return FS_ERR_DEVICE;
+            placed += cnt;
+        }
+        v0 = v1;
+    }
+    uint32_t e = 0;
+    ok = hipStreamSynchronize(back.s) == hipSuccess &&
+         hipMemcpy(&e, serr, sizeof e, hipMemcpyDeviceToHost) == hipSuccess;
+    return ok && e == 0 && placed == n ? FS_OK : FS_ERR_DEVICE;
 }
 
 }  // extern "C"

@@ -145,3 +145,48 @@ def test_host_stream_sort_large_is_sorted_permutation(gpu):
         counts_in += np.bincount(k[a:a + step], minlength=65536)
         counts_out += np.bincount(o, minlength=65536)
     assert np.array_equal(counts_in, counts_out)
+
+
+# ---- out-of-core sort of 32- and 64-bit keys (MSD spill) ----------------------------
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_host_sort_wide_keys_matches_oracle(gpu, bits):
+    """Several device ranges (device_keys far below n), ragged batches, the
+    three wide distributions (uniform; values below 2^20, whose top bits all
+    agree; 90% from 256 hot values), against the oracle byte for byte."""
+    ws = fs.Workspace(gpu)
+    for di, dist in enumerate(fsgen.DISTS_WIDE):
+        n = 3 * (1 << 20) + 4321
+        k = fsgen.keys_host(dist, bits, n, fsgen.seed_for(7, di))
+        src = torch.from_numpy(k).pin_memory()
+        out = fs.sort_host(src, batch_keys=(1 << 20) + 3, device_keys=1 << 19, workspace=ws, device=gpu)
+        assert np.array_equal(out.numpy(), oracle.sort(k)), (bits, dist)
+        assert ws.error_word() == 0
+
+
+def test_host_sort_wide_edges(gpu):
+    rng = np.random.default_rng(4)
+    for bits, dt in ((32, np.uint32), (64, np.uint64)):
+        for n in (0, 1, 7, 1000):
+            k = rng.integers(0, 1 << 63, n, dtype=np.uint64).astype(dt)
+            out = fs.sort_host(torch.from_numpy(k), batch_keys=64, device_keys=256, device=gpu)
+            assert np.array_equal(out.numpy(), np.sort(k)), (bits, n)
+        eq = np.full(100_000, 0xDEADBEEF, dtype=dt)  # every key equal: a copy
+        assert np.array_equal(fs.sort_host(torch.from_numpy(eq), device_keys=16, device=gpu).numpy(), eq)
+    # one histogram bin with more keys than a device range holds
+    k = fsgen.keys_host("hot90", 32, 200_000, 3)
+    with pytest.raises(fs.FsError) as e:
+        fs.sort_host(torch.from_numpy(k), batch_keys=1 << 16, device_keys=1024, device=gpu)
+    assert e.value.status == fs.FS_ERR_UNSUPPORTED
+
+
+def test_host_sort_wide_large_matches_threaded_oracle(gpu):
+    """2^30 host-resident u32 keys (4 GiB) through 2^28-key device ranges,
+    against the oracle (its threaded variant, pinned byte-equal to the
+    single-threaded one)."""
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint32, pin_memory=True)
+    src.copy_(fsgen.keys_device("uniform", 32, n, fsgen.seed_for(7, 9), device=gpu))
+    out = fs.sort_host(src, batch_keys=1 << 26, device_keys=1 << 28, device=gpu)
+    want = oracle.sort_mt(src.numpy(), threads=16)
+    assert np.array_equal(out.numpy(), want)
