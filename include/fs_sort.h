@@ -261,9 +261,13 @@ fs_status fs_sort_segmented_tuned(const fs_segment *d_segments, uint32_t num_seg
  *   v < 2^16.  keys: device, n 16-bit keys.  d_hist: device, 65536 uint64,
  *   8-byte aligned, caller-initialised (zero it before the first batch);
  *   must not overlap keys or the workspace.  Workspace as for every call
- *   (its size depends on n only).  n == 0 adds nothing.
+ *   (its size depends on n only).  n == 0 adds nothing.  flags: a key order
+ *   (FS_FLAG_SIGNED / FS_FLAG_FLOAT / FS_FLAG_DESCENDING): the histogram
+ *   then counts the order-mapped keys, bin v holding the keys of rank v in
+ *   that order; every batch of one histogram, and its expansion, must use
+ *   the same flags.
  */
-fs_status fs_hist16_accumulate(const void *keys, uint64_t n, uint64_t *d_hist, void *workspace,
+fs_status fs_hist16_accumulate(const void *keys, uint64_t n, unsigned flags, uint64_t *d_hist, void *workspace,
                                size_t *workspace_bytes, void *stream);
 
 /*
@@ -280,10 +284,12 @@ fs_status fs_hist16_prefix(const uint64_t *d_hist, uint64_t *d_prefix, void *str
  *   d_prefix[v] <= i < d_prefix[v + 1].  keys_out: device, count 16-bit
  *   keys, not overlapping d_prefix.  Positions at or beyond the total
  *   d_prefix[65536] are left unwritten.  Any range may be asked for, in any
- *   order, so the output can be produced in pieces.
+ *   order, so the output can be produced in pieces.  flags: the key order
+ *   the histogram was accumulated with (the keys written are the caller's
+ *   bits).
  */
-fs_status fs_expand16(const uint64_t *d_prefix, uint64_t first, uint64_t count, void *keys_out,
-                      void *stream);
+fs_status fs_expand16(const uint64_t *d_prefix, uint64_t first, uint64_t count, unsigned flags,
+                      void *keys_out, void *stream);
 
 /*
  * fs_sort16_host: ascending sort of n 16-bit keys that live in HOST memory
@@ -299,10 +305,11 @@ fs_status fs_expand16(const uint64_t *d_prefix, uint64_t first, uint64_t count, 
  *   kernels (they may be the same stream; NULL = the default stream).
  *   The workspace size depends on batch_keys only.  Unlike the other calls
  *   this one BLOCKS until h_keys_out holds the result (both streams are
- *   synchronised).  n == 0 is FS_OK and a no-op.
+ *   synchronised).  n == 0 is FS_OK and a no-op.  flags: key order, as for
+ *   fs_sort_keys.
  */
 fs_status fs_sort16_host(const void *h_keys_in, void *h_keys_out, uint64_t n, uint64_t batch_keys,
-                         void *workspace, size_t *workspace_bytes, void *copy_stream,
+                         unsigned flags, void *workspace, size_t *workspace_bytes, void *copy_stream,
                          void *compute_stream);
 
 /*
@@ -324,11 +331,12 @@ fs_status fs_sort16_host(const void *h_keys_in, void *h_keys_out, uint64_t n, ui
  *   key is equal the input is copied.  FS_ERR_UNSUPPORTED when one bin of
  *   the histogram holds more than device_keys keys.  The workspace size
  *   depends on batch_keys and device_keys.  Blocks until h_keys_out holds
- *   the result.  n == 0 is FS_OK and a no-op.
+ *   the result.  n == 0 is FS_OK and a no-op.  flags: key order, as for
+ *   fs_sort_keys (the spill then works on order-mapped keys).
  */
 fs_status fs_sort_host(const void *h_keys_in, void *h_keys_out, uint64_t n, int key_bits, uint64_t batch_keys,
-                       uint64_t device_keys, void *workspace, size_t *workspace_bytes, void *copy_stream,
-                       void *compute_stream);
+                       uint64_t device_keys, unsigned flags, void *workspace, size_t *workspace_bytes,
+                       void *copy_stream, void *compute_stream);
 
 const char *fs_status_string(fs_status s);
 

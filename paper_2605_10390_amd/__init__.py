@@ -73,15 +73,15 @@ def lib():
     L.fs_sort_keys_wide.restype = i32
     L.fs_sort_pairs_wide.argtypes = [vp, vp, vp, vp, u64, i32, i32, ctypes.c_uint, vp, sz, vp]
     L.fs_sort_pairs_wide.restype = i32
-    L.fs_hist16_accumulate.argtypes = [vp, u64, vp, vp, sz, vp]
+    L.fs_hist16_accumulate.argtypes = [vp, u64, ctypes.c_uint, vp, vp, sz, vp]
     L.fs_hist16_accumulate.restype = i32
     L.fs_hist16_prefix.argtypes = [vp, vp, vp]
     L.fs_hist16_prefix.restype = i32
-    L.fs_expand16.argtypes = [vp, u64, u64, vp, vp]
+    L.fs_expand16.argtypes = [vp, u64, u64, ctypes.c_uint, vp, vp]
     L.fs_expand16.restype = i32
-    L.fs_sort16_host.argtypes = [vp, vp, u64, u64, vp, sz, vp, vp]
+    L.fs_sort16_host.argtypes = [vp, vp, u64, u64, ctypes.c_uint, vp, sz, vp, vp]
     L.fs_sort16_host.restype = i32
-    L.fs_sort_host.argtypes = [vp, vp, u64, i32, u64, u64, vp, sz, vp, vp]
+    L.fs_sort_host.argtypes = [vp, vp, u64, i32, u64, u64, ctypes.c_uint, vp, sz, vp, vp]
     L.fs_sort_host.restype = i32
     L.fs_status_string.argtypes = [i32]
     L.fs_status_string.restype = ctypes.c_char_p
@@ -457,7 +457,7 @@ def sort_segmented(segments, workspace=None, tuning=None, key_type=None, descend
 # batches is sorted by accumulating their histograms and expanding the sum.
 
 def _u16(t, what):
-    if t.dtype not in (torch.uint16, torch.int16):
+    if t.dtype not in (torch.uint16, torch.int16, torch.float16, torch.bfloat16):
         raise TypeError(f"{what} must hold 16-bit keys, not {t.dtype}")
 
 
@@ -466,8 +466,9 @@ def new_hist16(device="cuda"):
     return torch.zeros(65536, dtype=torch.int64, device=device)
 
 
-def hist16_accumulate(keys, hist, workspace=None):
-    """hist[v] += number of keys equal to v (keys: 1-D 16-bit device tensor)."""
+def hist16_accumulate(keys, hist, workspace=None, key_type=None, descending=False):
+    """hist[v] += number of keys of rank v in the key order (unsigned
+    ascending: the keys equal to v); keys: 1-D 16-bit device tensor."""
     _check_dev(keys, hist)
     _u16(keys, "keys")
     if hist.dtype != torch.int64 or hist.numel() != 65536:
@@ -475,13 +476,14 @@ def hist16_accumulate(keys, hist, workspace=None):
     n = keys.numel()
     L = lib()
     size = ctypes.c_size_t(0)
-    st = L.fs_hist16_accumulate(None, n, None, None, ctypes.byref(size), None)
+    flags = order_flags(keys, key_type, descending)
+    st = L.fs_hist16_accumulate(None, n, flags, None, None, ctypes.byref(size), None)
     if st != FS_OK:
         raise FsError(st, "fs_hist16_accumulate (workspace query)")
     ws = workspace or Workspace(keys.device)
     buf = ws.get(size.value)
     size = ctypes.c_size_t(buf.numel())
-    st = L.fs_hist16_accumulate(_ptr(keys), n, _ptr(hist), _ptr(buf), ctypes.byref(size), _stream(keys))
+    st = L.fs_hist16_accumulate(_ptr(keys), n, flags, _ptr(hist), _ptr(buf), ctypes.byref(size), _stream(keys))
     if st != FS_OK:
         raise FsError(st, "fs_hist16_accumulate")
     return hist
@@ -498,15 +500,17 @@ def hist16_prefix(hist, prefix=None):
     return prefix
 
 
-def expand16(prefix, first, count, out=None):
-    """Sorted positions [first, first + count) of the multiset `prefix` describes."""
+def expand16(prefix, first, count, out=None, key_type="unsigned", descending=False):
+    """Sorted positions [first, first + count) of the multiset `prefix`
+    describes (key_type/descending: the order its histogram was built in)."""
     _check_dev(prefix)
     out = torch.empty(int(count), dtype=torch.uint16, device=prefix.device) if out is None else out
     _check_dev(out)
     _u16(out, "out")
     if out.numel() < count:
         raise ValueError("out is shorter than count")
-    st = lib().fs_expand16(_ptr(prefix), int(first), int(count), _ptr(out), _stream(prefix))
+    flags = order_flags(out, key_type, descending)
+    st = lib().fs_expand16(_ptr(prefix), int(first), int(count), flags, _ptr(out), _stream(prefix))
     if st != FS_OK:
         raise FsError(st, "fs_expand16")
     return out
@@ -514,13 +518,14 @@ def expand16(prefix, first, count, out=None):
 
 def sort16_host_workspace_bytes(batch_keys):
     size = ctypes.c_size_t(0)
-    st = lib().fs_sort16_host(None, None, 0, int(batch_keys), None, ctypes.byref(size), None, None)
+    st = lib().fs_sort16_host(None, None, 0, int(batch_keys), 0, None, ctypes.byref(size), None, None)
     if st != FS_OK:
         raise FsError(st, "fs_sort16_host (workspace query)")
     return size.value
 
 
-def sort16_host(keys, out=None, batch_keys=1 << 26, workspace=None, copy_stream=None, device="cuda"):
+def sort16_host(keys, out=None, batch_keys=1 << 26, workspace=None, copy_stream=None, device="cuda",
+                key_type=None, descending=False):
     """Sort 16-bit keys held in HOST memory (a CPU tensor, ideally pinned),
     streaming them through the device in batches of `batch_keys`.  `out` may
     be `keys` itself (in-place).  Blocks until `out` holds the result."""
@@ -538,16 +543,16 @@ def sort16_host(keys, out=None, batch_keys=1 << 26, workspace=None, copy_stream=
     size = ctypes.c_size_t(buf.numel())
     xs = copy_stream if copy_stream is not None else torch.cuda.Stream(dev)
     cs = torch.cuda.current_stream(dev)
-    st = lib().fs_sort16_host(_ptr(keys), _ptr(out), keys.numel(), int(batch_keys), _ptr(buf),
-                              ctypes.byref(size), ctypes.c_void_p(xs.cuda_stream),
-                              ctypes.c_void_p(cs.cuda_stream))
+    st = lib().fs_sort16_host(_ptr(keys), _ptr(out), keys.numel(), int(batch_keys),
+                              order_flags(keys, key_type, descending), _ptr(buf), ctypes.byref(size),
+                              ctypes.c_void_p(xs.cuda_stream), ctypes.c_void_p(cs.cuda_stream))
     if st != FS_OK:
         raise FsError(st, "fs_sort16_host")
     return out
 
 
 def sort_host(keys, out=None, batch_keys=1 << 26, device_keys=1 << 30, workspace=None, copy_stream=None,
-              device="cuda"):
+              device="cuda", key_type=None, descending=False):
     """Sort 32- or 64-bit keys held in HOST memory (a CPU tensor, ideally
     pinned) that need not fit on the device: an MSD spill through ranges of
     at most `device_keys` keys.  Blocks until `out` holds the result."""
@@ -562,8 +567,9 @@ def sort_host(keys, out=None, batch_keys=1 << 26, device_keys=1 << 30, workspace
     dev = torch.device(device)
     L = lib()
     size = ctypes.c_size_t(0)
-    st = L.fs_sort_host(None, None, 0, bits, int(batch_keys), int(device_keys), None, ctypes.byref(size), None,
-                        None)
+    flags = order_flags(keys, key_type, descending)
+    st = L.fs_sort_host(None, None, 0, bits, int(batch_keys), int(device_keys), flags, None, ctypes.byref(size),
+                        None, None)
     if st != FS_OK:
         raise FsError(st, "fs_sort_host (workspace query)")
     ws = workspace or Workspace(dev)
@@ -571,8 +577,9 @@ def sort_host(keys, out=None, batch_keys=1 << 26, device_keys=1 << 30, workspace
     size = ctypes.c_size_t(buf.numel())
     xs = copy_stream if copy_stream is not None else torch.cuda.Stream(dev)
     cs = torch.cuda.current_stream(dev)
-    st = L.fs_sort_host(_ptr(keys), _ptr(out), keys.numel(), bits, int(batch_keys), int(device_keys), _ptr(buf),
-                        ctypes.byref(size), ctypes.c_void_p(xs.cuda_stream), ctypes.c_void_p(cs.cuda_stream))
+    st = L.fs_sort_host(_ptr(keys), _ptr(out), keys.numel(), bits, int(batch_keys), int(device_keys), flags,
+                        _ptr(buf), ctypes.byref(size), ctypes.c_void_p(xs.cuda_stream),
+                        ctypes.c_void_p(cs.cuda_stream))
     if st != FS_OK:
         raise FsError(st, "fs_sort_host")
     return out

@@ -101,7 +101,7 @@ constexpr uint64_t kMaxKeys = 1ull << 36;
 
 // Key order masks of order_map (fs_device.hpp) for the order flags; false
 // for an unknown flag or SIGNED together with FLOAT.
-static bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* neg) {
+bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* neg) {
     const unsigned known = FS_FLAG_SIGNED | FS_FLAG_FLOAT | FS_FLAG_DESCENDING;
     if ((flags & ~known) || ((flags & FS_FLAG_SIGNED) && (flags & FS_FLAG_FLOAT))) return false;
     if ((flags & FS_FLAG_FLOAT) && key_bits == 8) return false;  // no 8-bit IEEE format

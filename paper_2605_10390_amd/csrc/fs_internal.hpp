@@ -102,6 +102,10 @@ hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes,
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
                               uint32_t* wrap_word, hipStream_t s);
 
+// order_map masks (pos, neg) of the key order flags for key_bits-wide keys;
+// false for an unknown flag, SIGNED with FLOAT, or FLOAT with 8-bit keys
+bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* neg);
+
 // ---- multi-word keys (wide.hip) ---------------------------------------------
 // perm_bytes: 4 or 8 (width of a permutation entry)
 hipError_t launch_iota(void* perm, int perm_bytes, uint64_t n, hipStream_t s);

@@ -38,12 +38,13 @@ size_t accumulate_bytes(uint64_t n) {
 }
 
 // d_hist += histogram of keys[0, n) (n > 0), with `ws` of accumulate_bytes(n)
-hipError_t enqueue_accumulate(const uint16_t* keys, uint64_t n, uint64_t* d_hist, char* ws, hipStream_t s) {
+hipError_t enqueue_accumulate(const uint16_t* keys, uint64_t n, uint64_t* d_hist, char* ws, hipStream_t s,
+                              uint32_t opos = 0, uint32_t oneg = 0) {
     const uint32_t groups = hist_groups(n);
     uint32_t* part = reinterpret_cast<uint32_t*>(ws);
     uint32_t* wrap = reinterpret_cast<uint32_t*>(ws + align256(4ull * groups * kHist16Words));
     hipError_t e = launch_fill_u32(wrap, 2ull * kHist16Words, 0, s);
-    if (e == hipSuccess) e = launch_hist16c(keys, n, groups, part, wrap, wrap + kHist16Words, s);
+    if (e == hipSuccess) e = launch_hist16c(keys, n, groups, part, wrap, wrap + kHist16Words, s, opos, oneg);
     if (e == hipSuccess) e = launch_merge16(part, groups, wrap, wrap + kHist16Words, d_hist, s, true);
     return e;
 }
@@ -72,10 +73,11 @@ struct SlotEvents {
 
 extern "C" {
 
-fs_status fs_hist16_accumulate(const void* keys, uint64_t n, uint64_t* d_hist, void* workspace,
+fs_status fs_hist16_accumulate(const void* keys, uint64_t n, unsigned flags, uint64_t* d_hist, void* workspace,
                                size_t* workspace_bytes, void* stream) {
     using namespace fs;
-    if (!workspace_bytes || n > kMaxStreamKeys) return FS_ERR_INVALID_ARG;
+    uint64_t opos, oneg;
+    if (!workspace_bytes || n > kMaxStreamKeys || !order_masks(flags, 16, &opos, &oneg)) return FS_ERR_INVALID_ARG;
     const size_t need = accumulate_bytes(n);
     if (!workspace) {
         *workspace_bytes = need;
@@ -91,7 +93,7 @@ fs_status fs_hist16_accumulate(const void* keys, uint64_t n, uint64_t* d_hist, v
     if ((k < h + kHistBytes && h < k + 2 * n) || (w < h + kHistBytes && h < w + need))
         return FS_ERR_INVALID_ARG;
     if (enqueue_accumulate(static_cast<const uint16_t*>(keys), n, d_hist, static_cast<char*>(workspace),
-                           static_cast<hipStream_t>(stream)) != hipSuccess)
+                           static_cast<hipStream_t>(stream), (uint32_t)opos, (uint32_t)oneg) != hipSuccess)
         return FS_ERR_DEVICE;
     return FS_OK;
 }
@@ -105,23 +107,28 @@ fs_status fs_hist16_prefix(const uint64_t* d_hist, uint64_t* d_prefix, void* str
     return FS_OK;
 }
 
-fs_status fs_expand16(const uint64_t* d_prefix, uint64_t first, uint64_t count, void* keys_out, void* stream) {
+fs_status fs_expand16(const uint64_t* d_prefix, uint64_t first, uint64_t count, unsigned flags, void* keys_out,
+                      void* stream) {
     using namespace fs;
-    if (count > kMaxStreamKeys || first > kMaxStreamKeys) return FS_ERR_INVALID_ARG;
+    uint64_t opos, oneg;
+    if (count > kMaxStreamKeys || first > kMaxStreamKeys || !order_masks(flags, 16, &opos, &oneg))
+        return FS_ERR_INVALID_ARG;
     if (count == 0) return FS_OK;
     if (!d_prefix || !keys_out || !aligned(d_prefix, 8) || !aligned(keys_out, 2)) return FS_ERR_INVALID_ARG;
     const uintptr_t p = reinterpret_cast<uintptr_t>(d_prefix), o = reinterpret_cast<uintptr_t>(keys_out);
     if (p < o + 2 * count && o < p + kPrefixBytes) return FS_ERR_INVALID_ARG;
-    if (launch_expand16(d_prefix, static_cast<uint16_t*>(keys_out), first, count,
-                        static_cast<hipStream_t>(stream)) != hipSuccess)
+    if (launch_expand16(d_prefix, static_cast<uint16_t*>(keys_out), first, count, static_cast<hipStream_t>(stream),
+                        (uint32_t)opos, (uint32_t)oneg) != hipSuccess)
         return FS_ERR_DEVICE;
     return FS_OK;
 }
 
-fs_status fs_sort16_host(const void* h_keys_in, void* h_keys_out, uint64_t n, uint64_t batch_keys,
+fs_status fs_sort16_host(const void* h_keys_in, void* h_keys_out, uint64_t n, uint64_t batch_keys, unsigned flags,
                          void* workspace, size_t* workspace_bytes, void* copy_stream, void* compute_stream) {
     using namespace fs;
-    if (!workspace_bytes || n > kMaxStreamKeys || batch_keys == 0 || batch_keys > kMaxStreamKeys)
+    uint64_t opos, oneg;
+    if (!workspace_bytes || n > kMaxStreamKeys || batch_keys == 0 || batch_keys > kMaxStreamKeys ||
+        !order_masks(flags, 16, &opos, &oneg))
         return FS_ERR_INVALID_ARG;
     const uint64_t batch = (batch_keys + 7) / 8 * 8;  // slots start 16-byte aligned
     const size_t slot_bytes = align256(2 * batch);
@@ -164,7 +171,7 @@ fs_status fs_sort16_host(const void* h_keys_in, void* h_keys_out, uint64_t n, ui
         ok = ok && hipMemcpyAsync(slot[i], in + off, 2 * len, hipMemcpyHostToDevice, xs) == hipSuccess;
         ok = ok && hipEventRecord(ev.filled[i], xs) == hipSuccess;
         ok = ok && hipStreamWaitEvent(cs, ev.filled[i], 0) == hipSuccess;
-        ok = ok && enqueue_accumulate(slot[i], len, hist, acc_ws, cs) == hipSuccess;
+        ok = ok && enqueue_accumulate(slot[i], len, hist, acc_ws, cs, (uint32_t)opos, (uint32_t)oneg) == hipSuccess;
         ok = ok && hipEventRecord(ev.emptied[i], cs) == hipSuccess;
     }
     ok = ok && launch_scan16(hist, prefix, cs) == hipSuccess;
@@ -175,7 +182,7 @@ fs_status fs_sort16_host(const void* h_keys_in, void* h_keys_out, uint64_t n, ui
         const int i = (int)(c & 1);
         const uint64_t off = c * batch, len = std::min(batch, n - off);
         if (c >= 2) ok = hipStreamWaitEvent(cs, ev.emptied[i], 0) == hipSuccess;
-        ok = ok && launch_expand16(prefix, slot[i], off, len, cs) == hipSuccess;
+        ok = ok && launch_expand16(prefix, slot[i], off, len, cs, (uint32_t)opos, (uint32_t)oneg) == hipSuccess;
         ok = ok && hipEventRecord(ev.filled[i], cs) == hipSuccess;
         ok = ok && hipStreamWaitEvent(xs, ev.filled[i], 0) == hipSuccess;
         ok = ok && hipMemcpyAsync(out + off, slot[i], 2 * len, hipMemcpyDeviceToHost, xs) == hipSuccess;
@@ -200,15 +207,19 @@ namespace {
 
 constexpr int kHostThreads = 256;
 
+// Every kernel here works on the order-mapped key (order_map with opos,
+// oneg; both 0 for unsigned ascending) and moves the caller's bits.
+
 // OR and AND of every key (the bits on which keys differ are OR ^ AND)
 template <typename K>
 __global__ __launch_bounds__(kHostThreads) void k_or_and(const K* __restrict__ keys, uint64_t n,
-                                                         unsigned long long* acc) {
+                                                         unsigned long long* acc, uint64_t opos, uint64_t oneg) {
     uint64_t o = 0, a = ~0ull;
     const uint64_t stride = (uint64_t)gridDim.x * kHostThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kHostThreads + threadIdx.x; i < n; i += stride) {
-        o |= (uint64_t)keys[i];
-        a &= (uint64_t)keys[i];
+        const uint64_t t = order_map<K>(keys[i], (K)opos, (K)oneg);
+        o |= t;
+        a &= t;
     }
     for (int off = 32; off > 0; off >>= 1) {
         o |= __shfl_xor(o, off, 64);
@@ -224,13 +235,14 @@ __global__ __launch_bounds__(kHostThreads) void k_or_and(const K* __restrict__ k
 template <typename K>
 __global__ __launch_bounds__(kHostThreads) void k_hist_window(const K* __restrict__ keys, uint64_t n, int shift,
                                                               uint32_t* __restrict__ part, uint32_t* wrap_lo,
-                                                              uint32_t* wrap_word) {
+                                                              uint32_t* wrap_word, uint64_t opos, uint64_t oneg) {
     __shared__ uint32_t cnt[kHist16Words];
     for (int i = threadIdx.x; i < kHist16Words; i += kHostThreads) cnt[i] = 0;
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * kHostThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kHostThreads + threadIdx.x; i < n; i += stride)
-        hist16_add(cnt, (uint32_t)(((uint64_t)keys[i] >> shift) & 0xFFFFu), 1u, wrap_lo, wrap_word);
+        hist16_add(cnt, (uint32_t)(((uint64_t)order_map<K>(keys[i], (K)opos, (K)oneg) >> shift) & 0xFFFFu), 1u,
+                   wrap_lo, wrap_word);
     __syncthreads();
     uint32_t* dst = part + (uint64_t)blockIdx.x * kHist16Words;
     for (int i = threadIdx.x; i < kHist16Words; i += kHostThreads) dst[i] = cnt[i];
@@ -244,13 +256,13 @@ template <typename K>
 __global__ __launch_bounds__(kHostThreads) void k_select_range(const K* __restrict__ keys, uint64_t n, int shift,
                                                                uint32_t lo, uint32_t hi, K* __restrict__ out,
                                                                uint64_t cap, unsigned long long* count,
-                                                               uint32_t* err) {
+                                                               uint32_t* err, uint64_t opos, uint64_t oneg) {
     __shared__ unsigned long long s_base;
     __shared__ uint32_t s_cnt;
     const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint64_t c0 = (uint64_t)blockIdx.x * per, c1 = c0 + per < n ? c0 + per : n;
     auto in_range = [&](K k) {
-        const uint32_t v = (uint32_t)(((uint64_t)k >> shift) & 0xFFFFu);
+        const uint32_t v = (uint32_t)(((uint64_t)order_map<K>(k, (K)opos, (K)oneg) >> shift) & 0xFFFFu);
         return v >= lo && v < hi;
     };
     if (threadIdx.x == 0) s_cnt = 0;
@@ -295,10 +307,12 @@ uint32_t host_grid(uint64_t n) {
 extern "C" {
 
 fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int key_bits, uint64_t batch_keys,
-                       uint64_t device_keys, void* workspace, size_t* workspace_bytes, void* copy_stream,
-                       void* compute_stream) {
+                       uint64_t device_keys, unsigned flags, void* workspace, size_t* workspace_bytes,
+                       void* copy_stream, void* compute_stream) {
     using namespace fs;
     if (key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
+    uint64_t opos, oneg;
+    if (!order_masks(flags, key_bits, &opos, &oneg)) return FS_ERR_INVALID_ARG;
     if (!workspace_bytes || n > kMaxStreamKeys || batch_keys == 0 || batch_keys > kMaxStreamKeys ||
         device_keys == 0 || device_keys > kMaxStreamKeys)
         return FS_ERR_INVALID_ARG;
@@ -392,8 +406,10 @@ fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int 
          launch_fill_u32(reinterpret_cast<uint32_t*>(acc + 1), 2, 0xFFFFFFFFu, cs) == hipSuccess &&
          launch_fill_u32(serr, 1, 0u, cs) == hipSuccess;
     stream_input([&](const char* keys, uint64_t len) {
-        if (kb == 4) k_or_and<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>((const uint32_t*)keys, len, acc);
-        else k_or_and<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>((const uint64_t*)keys, len, acc);
+        if (kb == 4)
+            k_or_and<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>((const uint32_t*)keys, len, acc, opos, oneg);
+        else
+            k_or_and<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>((const uint64_t*)keys, len, acc, opos, oneg);
         return launch_ok();
     });
     unsigned long long oa_h[2] = {0, 0};
@@ -414,10 +430,10 @@ fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int 
         if (launch_fill_u32(wrap, 2ull * kHist16Words, 0, cs) != hipSuccess) return false;
         if (kb == 4)
             k_hist_window<uint32_t><<<g, kHostThreads, 0, cs>>>((const uint32_t*)keys, len, shift, part, wrap,
-                                                                wrap + kHist16Words);
+                                                                wrap + kHist16Words, opos, oneg);
         else
             k_hist_window<uint64_t><<<g, kHostThreads, 0, cs>>>((const uint64_t*)keys, len, shift, part, wrap,
-                                                                wrap + kHist16Words);
+                                                                wrap + kHist16Words, opos, oneg);
         return launch_ok() && launch_merge16(part, g, wrap, wrap + kHist16Words, hist, cs, true) == hipSuccess;
     });
     std::vector<uint64_t> h(65536);
@@ -436,10 +452,10 @@ fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int 
             stream_input([&](const char* keys, uint64_t len) {
                 if (kb == 4)
                     k_select_range<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>(
-                        (const uint32_t*)keys, len, shift, v0, v1, (uint32_t*)range, cnt, acc + 2, serr);
+                        (const uint32_t*)keys, len, shift, v0, v1, (uint32_t*)range, cnt, acc + 2, serr, opos, oneg);
                 else
                     k_select_range<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>(
-                        (const uint64_t*)keys, len, shift, v0, v1, (uint64_t*)range, cnt, acc + 2, serr);
+                        (const uint64_t*)keys, len, shift, v0, v1, (uint64_t*)range, cnt, acc + 2, serr, opos, oneg);
                 return launch_ok();
             });
             unsigned long long got = 0;
@@ -448,7 +464,7 @@ fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int 
             // the previous range's copy back must have left the sorted buffer
             ok = hipStreamWaitEvent(cs, back.drained, 0) == hipSuccess;
             size_t ib = inner;
-            if (!ok || fs_sort_keys(range, sorted, cnt, key_bits, 0, ws + o_inner, &ib, cs) != FS_OK)
+            if (!ok || fs_sort_keys(range, sorted, cnt, key_bits, flags, ws + o_inner, &ib, cs) != FS_OK)
                 return FS_ERR_DEVICE;
             uint32_t e = 0;  // the range sort's error word
             ok = hipEventRecord(back.sorted, cs) == hipSuccess &&

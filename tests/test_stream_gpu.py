@@ -190,3 +190,35 @@ def test_host_sort_wide_large_matches_threaded_oracle(gpu):
     out = fs.sort_host(src, batch_keys=1 << 26, device_keys=1 << 28, device=gpu)
     want = oracle.sort_mt(src.numpy(), threads=16)
     assert np.array_equal(out.numpy(), want)
+
+
+# ---- key orders in the stream and out-of-core sorts ------------------------------
+
+ORDERS = [("signed", False), ("float", False), ("float", True), ("unsigned", True)]
+
+
+@pytest.mark.parametrize("key_type,desc", ORDERS)
+def test_stream_sorts_in_every_order(gpu, key_type, desc):
+    """The accumulated histogram / expansion, the 16-bit host sort and the
+    out-of-core 32/64-bit sort, each in another key order, against
+    oracle.sort_ordered (random bit patterns: floats include NaNs,
+    infinities and both zeros)."""
+    rng = np.random.default_rng(31)
+    n = (1 << 20) + 333
+    k16 = rng.integers(0, 1 << 16, n, dtype=np.uint64).astype(np.uint16)
+    want16 = oracle.sort_ordered(k16, key_type=key_type, descending=desc)
+    hist = fs.new_hist16(gpu)
+    for a in range(0, n, 300_000):
+        fs.hist16_accumulate(dev(k16[a:a + 300_000]), hist, key_type=key_type, descending=desc)
+    prefix = fs.hist16_prefix(hist)
+    assert np.array_equal(host(fs.expand16(prefix, 0, n, key_type=key_type, descending=desc)), want16)
+    part = host(fs.expand16(prefix, 1000, 5000, key_type=key_type, descending=desc))
+    assert np.array_equal(part, want16[1000:6000])
+    out16 = fs.sort16_host(torch.from_numpy(k16).pin_memory(), batch_keys=1 << 18, device=gpu,
+                           key_type=key_type, descending=desc)
+    assert np.array_equal(out16.numpy(), want16)
+    for bits, dt in ((32, np.uint32), (64, np.uint64)):
+        k = rng.integers(0, 1 << 63, n, dtype=np.uint64).astype(dt) * dt(2) + rng.integers(0, 2, n).astype(dt)
+        out = fs.sort_host(torch.from_numpy(k).pin_memory(), batch_keys=1 << 18, device_keys=1 << 18,
+                           device=gpu, key_type=key_type, descending=desc)
+        assert np.array_equal(out.numpy(), oracle.sort_ordered(k, key_type=key_type, descending=desc)), bits
