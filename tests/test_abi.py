@@ -54,3 +54,29 @@ def test_argument_errors_need_no_gpu():
     for flags in (0, 1, 4, 5):
         assert lib.fs_sort_keys(None, None, 10, 8, flags, None, ctypes.byref(size), None) == 0
     assert lib.fs_sort_keys(None, None, 10, 8, 2, None, ctypes.byref(size), None) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfsort.so not built")
+def test_extended_entry_points_check_arguments_without_a_gpu():
+    """Workspace queries of the multi-word, stream and out-of-core sorts
+    answer, and bad widths or flags are refused, before any device call."""
+    lib = ctypes.CDLL(LIB)
+    vp, u64, i32, ui = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    lib.fs_sort_keys_wide.argtypes = [vp, vp, u64, i32, ui, vp, sz, vp]
+    lib.fs_sort_host.argtypes = [vp, vp, u64, i32, u64, u64, ui, vp, sz, vp, vp]
+    lib.fs_sort16_host.argtypes = [vp, vp, u64, u64, ui, vp, sz, vp, vp]
+    lib.fs_hist16_accumulate.argtypes = [vp, u64, ui, vp, vp, sz, vp]
+    size = ctypes.c_size_t(0)
+    for words in (0, 65):
+        assert lib.fs_sort_keys_wide(None, None, 100, words, 0, None, ctypes.byref(size), None) == 1
+    assert lib.fs_sort_keys_wide(None, None, 100, 3, 0, None, ctypes.byref(size), None) == 0
+    assert size.value > 0
+    assert lib.fs_sort_keys_wide(None, None, 100, 2, 3, None, ctypes.byref(size), None) == 1  # SIGNED|FLOAT
+    for bits in (8, 16, 24):
+        assert lib.fs_sort_host(None, None, 10, bits, 64, 64, 0, None, ctypes.byref(size), None, None) == 1
+    assert lib.fs_sort_host(None, None, 10, 32, 0, 64, 0, None, ctypes.byref(size), None, None) == 1
+    assert lib.fs_sort_host(None, None, 10, 64, 64, 64, 5, None, ctypes.byref(size), None, None) == 0
+    assert lib.fs_sort16_host(None, None, 10, 64, 8, None, ctypes.byref(size), None, None) == 1
+    assert lib.fs_hist16_accumulate(None, 10, 3, None, None, ctypes.byref(size), None) == 1
+    assert lib.fs_hist16_accumulate(None, 10, 2, None, None, ctypes.byref(size), None) == 0
