@@ -515,7 +515,7 @@ def main():
                            PMC_SUMMARY, cmd)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design in DESIGN.md, not a measured path)", file=sys.stderr)
+              "(multi-GPU sharding is designed, not measured)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "c3":

@@ -2,7 +2,7 @@
  * fs_profile.h -- per-kernel timing of the sort library (instrumentation).
  *
  * The paper reports sort latency as an average over repeated runs (Section
- * IV) and judges a sort by how much of the memory traffic it causes is
+ * IV) and rates a sort by how much of the memory traffic it causes is
  * useful (bandwidth efficiency, Equation beff, Section IV-F.1).  To measure
  * that per kernel, the library can record a HIP event pair around every
  * kernel it launches, on the stream the kernel is launched on.
