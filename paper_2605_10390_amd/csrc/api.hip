@@ -478,6 +478,7 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
     };
     const size_t o_err = take(4 * (1 + 256));
     const size_t o_small = take(4ull * nseg);
+    const size_t o_wave = take(4ull * nseg);
     const size_t o_expand = take(4ull * nseg);
     const uint64_t nx_max = std::min<uint64_t>(nseg, total_keys / kX16MinSplit);
     const size_t o_x16p = take(4ull * (nx_max + 1));
@@ -517,6 +518,7 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
     x.err = reinterpret_cast<uint32_t*>(w + o_err);
     x.ctr = x.err + 1;
     x.small_list = reinterpret_cast<uint32_t*>(w + o_small);
+    x.wave_list = reinterpret_cast<uint32_t*>(w + o_wave);
     x.expand_list = reinterpret_cast<uint32_t*>(w + o_expand);
     x.x16_parts = reinterpret_cast<uint32_t*>(w + o_x16p);
     x.x16_hist = reinterpret_cast<uint32_t*>(w + o_x16h);

@@ -134,6 +134,7 @@ hipError_t timed(int kind, uint64_t keys, hipStream_t s, F&& launch) {
 
 // ---- batched segmented sort (segmented.hip) --------------------------------
 constexpr uint32_t kSegSmallBytes = 32768;           // LDS bytes per buffer of a small segment
+constexpr uint32_t kSegWaveMaxKeys = 64;  // segments this short take the wave bin
 constexpr uint64_t kSegMaxKeys = (1ull << 23) - 1;  // largest segment (look-back counts are 23-bit)
 constexpr uint32_t kSegMinSmallMax = 1024;         // least segment length a tuning may send to the large bin
 constexpr uint32_t kSegMinTile = 2048;             // smallest large-segment tile (sizes the tile arrays)
@@ -169,6 +170,7 @@ struct SegCtx {
     uint32_t* err;
     uint32_t* ctr;          // queue counters, tile totals, tickets
     uint32_t* small_list;   // [nseg]
+    uint32_t* wave_list;    // [nseg]: segments of at most kSegWaveMaxKeys keys
     uint32_t* expand_list;  // [nseg]: long segments from the front, the rest from the back
     uint32_t* x16_parts;    // [long segments + 1] part prefix
     uint32_t* x16_hist;     // [long segments][65536] exact bin counts

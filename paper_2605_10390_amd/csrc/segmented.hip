@@ -6,10 +6,11 @@
 // stand-alone sort would give it.  Segment descriptors live in device
 // memory, so the whole schedule is decided on the device:
 //   1. classify: each segment goes to one bin by width and length (bounds
-//      from the launch tuning, fs_seg_tuning): the 16-bit-digit bin (16-bit
-//      keys without payload, long enough), the LDS bin (short enough to fit
-//      in one workgroup's LDS), the one-workgroup bin or the large bin of its
-//      (key, value) class;
+//      from the launch tuning, fs_seg_tuning): the wave bin (at most 64
+//      keys), the 16-bit-digit bin (16-bit keys without payload, long
+//      enough), the LDS bin (short enough to fit in one workgroup's LDS), the
+//      one-workgroup bin or the large bin of its (key, value) class;
+//   1a. wave bin: one wave per segment ranks its keys in registers (k_seg_wave);
 //   2. 16-bit-digit bin: the segment's compressed 2^16-bin histogram is
 //      built in LDS and the sorted keys are written from it (one read and one
 //      write of HBM, no scatter); one workgroup per medium segment, 2^18-key
@@ -57,6 +58,8 @@ __host__ __device__ inline int ctr_x16_parts() { return 124; }  // parts of the 
 __host__ __device__ inline int ctr_wg(int c) { return 128 + c; }        // one-workgroup large segments queued
 __host__ __device__ inline int ctr_wg_taken(int c) { return 137 + c; }  //   and taken
 __host__ __device__ inline int ctr_wg_tmp(int c) { return 147 + 2 * c; }  // 64-bit temporary-pool bump (8-byte aligned)
+__host__ __device__ inline int ctr_wave() { return 166; }        // wave-bin segments queued
+__host__ __device__ inline int ctr_wave_taken() { return 167; }  //   and taken
 
 // ---------------------------------------------------------------------------
 // Key order of the call (order_map, fs_device.hpp): the kernels that touch
@@ -96,6 +99,10 @@ __global__ void k_seg_classify(SegCtx x) {
             continue;
         }
         const int kb = d.key_bits / 8, vb = d.val_bytes;
+        if (d.n <= kSegWaveMaxKeys) {  // one wave sorts it in registers
+            x.wave_list[atomicAdd(&x.ctr[ctr_wave()], 1u)] = s;
+            continue;
+        }
         const uint32_t small_max = x.small_max[kb == 2 ? 0 : kb == 4 ? 1 : 2];
         if (kb == 2 && vb == 0 && d.n >= x.expand_min) {
             // long segments (split over several workgroups) at the front
@@ -277,6 +284,61 @@ __device__ __forceinline__ void sort_small(const SegCtx& x, const fs_segment& d,
     lds_to_global<K, kSmallThreads>(kbuf(cur), static_cast<K*>(d.keys_out), n);
     if constexpr (kHasVals) lds_to_global<VS, kSmallThreads>(vbuf(cur), static_cast<VS*>(d.vals_out), n);
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Wave bin: segments of at most 64 keys, one per wave.  Lane i holds key i;
+// its output position is the number of keys of the segment that sort
+// before it (smaller keys, and equal keys of lower index: stable), counted
+// over the wave's registers with shuffles.  No LDS, no barrier.
+// ---------------------------------------------------------------------------
+constexpr int kWaveThreads = 256;
+
+__device__ __forceinline__ uint64_t load_elem(const void* p, uint32_t i, int bytes) {
+    if (bytes == 2) return to_global(static_cast<const uint16_t*>(p))[i];
+    if (bytes == 4) return to_global(static_cast<const uint32_t*>(p))[i];
+    return to_global(static_cast<const uint64_t*>(p))[i];
+}
+
+__device__ __forceinline__ void store_elem(void* p, uint32_t i, int bytes, uint64_t v) {
+    if (bytes == 2) to_global(static_cast<uint16_t*>(p))[i] = (uint16_t)v;
+    else if (bytes == 4) to_global(static_cast<uint32_t*>(p))[i] = (uint32_t)v;
+    else to_global(static_cast<uint64_t*>(p))[i] = v;
+}
+
+template <bool ORD>
+__global__ __launch_bounds__(kWaveThreads) void k_seg_wave(SegCtx x) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t count = x.ctr[ctr_wave()];
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(&x.ctr[ctr_wave_taken()], 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= count) break;
+        const fs_segment d = x.segs[x.wave_list[item]];
+        const uint32_t n = (uint32_t)d.n;
+        const int kb = (int)d.key_bits / 8, vb = (int)d.val_bytes;
+        const bool valid = lane < n;
+        const uint64_t k = valid ? load_elem(d.keys_in, lane, kb) : 0;
+        // the order-mapped key, as an unsigned value of the segment's width
+        uint64_t t = k;
+        if constexpr (ORD) {
+            const int w = kb == 2 ? 0 : kb == 4 ? 1 : 2;
+            const uint64_t top = k >> (8 * kb - 1);
+            t = k ^ (top ? x.ord_neg[w] : x.ord_pos[w]);
+            if (kb < 8) t &= (1ull << (8 * kb)) - 1;
+        }
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint64_t tj = ((uint64_t)__shfl((int)(uint32_t)(t >> 32), (int)j, 64) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)t, (int)j, 64);
+            rank += (tj < t || (tj == t && j < lane)) ? 1u : 0u;
+        }
+        if (valid) {
+            store_elem(d.keys_out, rank, kb, k);
+            if (vb) store_elem(d.vals_out, rank, vb, load_elem(d.vals_in, lane, vb));
+        }
+    }
 }
 
 template <bool ORD>
@@ -1447,6 +1509,7 @@ static hipError_t launch_bins(const SegCtx& x, const fs_seg_tuning& t, int cus, 
     k_seg_x16_hist<ORD><<<xg, kExpThreads, 0, s>>>(x);
     k_seg_x16_out<ORD><<<xg, kExpThreads, 0, s>>>(x);
     k_seg_expand16<ORD><<<xg, kExpThreads, 0, s>>>(x);
+    k_seg_wave<ORD><<<cus * 2, kWaveThreads, 0, s>>>(x);
     k_seg_small<ORD><<<cus * (int)t.small_wgs_per_cu, kSmallThreads, 0, s>>>(x);
     const int P = cus * (int)t.large_wgs_per_cu;
     const int it = (int)t.tile_items, th = (int)t.tile_threads;

@@ -268,3 +268,35 @@ def test_large_bin_histograms_start_from_zero(gpu):
         torch.cuda.synchronize()
         assert ws.error_word() == 0
         check(host, devs)
+
+
+def test_wave_bin_tiny_segments(gpu):
+    """Segments of 1..64 keys (the wave bin) of every width and payload,
+    with repeated keys, in every key order, next to longer segments."""
+    rng = np.random.default_rng(64)
+    specs = []
+    for i in range(300):
+        bits = (16, 32, 64)[i % 3]
+        vb = (0, 4, 8)[(i // 3) % 3]
+        n = int(rng.integers(1, 65)) if i % 10 else 64
+        specs.append((bits, vb, n))
+    specs += [(32, 4, 65), (16, 0, 5000)]
+    for key_type, desc in (("unsigned", False), ("signed", True), ("float", False)):
+        segs, want = [], []
+        for bits, vb, n in specs:
+            k = rng.integers(0, 1 << 63, n, dtype=np.uint64).astype({16: np.uint16, 32: np.uint32, 64: np.uint64}[bits])
+            k[: n // 3] = k[n // 3: 2 * (n // 3)]
+            v = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32 if vb == 4 else np.uint64) if vb else None
+            ki = torch.from_numpy(k).cuda()
+            vi = torch.from_numpy(v).cuda() if vb else None
+            segs.append((ki, torch.empty_like(ki), vi, torch.empty_like(vi) if vb else None))
+            want.append(oracle.sort_ordered(k, v, key_type=key_type, descending=desc))
+        ws = fs.sort_segmented(segs, key_type=key_type, descending=desc)
+        torch.cuda.synchronize()
+        assert ws.error_word() == 0
+        for (bits, vb, n), (_, ko, _, vo), w in zip(specs, segs, want):
+            if vo is None:
+                assert np.array_equal(ko.cpu().numpy(), w), (key_type, bits, vb, n)
+            else:
+                assert np.array_equal(ko.cpu().numpy(), w[0]), (key_type, bits, vb, n)
+                assert np.array_equal(vo.cpu().numpy(), w[1]), (key_type, bits, vb, n)
