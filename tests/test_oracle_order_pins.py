@@ -175,3 +175,33 @@ def test_wide_hand_ordered_two_word_keys():
         sh = f[rng.permutation(len(f128))]
         assert np.array_equal(oracle.sort_wide(sh, key_type="float"), f)
         assert np.array_equal(oracle.sort_wide(sh, key_type="float", descending=True), f[::-1])
+
+
+# ---- property-based pins (hypothesis) -----------------------------------------------
+import struct
+
+from hypothesis import given, settings, strategies as st
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.lists(st.floats(allow_nan=False, width=32), max_size=40), st.booleans())
+def test_float32_order_is_python_float_order(values, desc):
+    """Non-NaN binary32 values: the oracle's order is Python's float order
+    (ties between -0.0 and +0.0 broken by sign, equal bits by position)."""
+    bits = np.array([struct.unpack("<I", struct.pack("<f", v))[0] for v in values], dtype=np.uint32)
+    key = lambda i: (values[i], 0 if struct.pack("<f", values[i])[3] & 0x80 else 1)  # noqa: E731
+    want = sorted(range(len(values)), key=key, reverse=desc)
+    _, got = oracle.sort_ordered(bits, np.arange(len(values), dtype=np.uint32), key_type="float", descending=desc)
+    assert got.tolist() == want
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.lists(st.integers(min_value=-(1 << 127), max_value=(1 << 127) - 1), max_size=30), st.booleans())
+def test_two_word_signed_order_is_python_int_order(values, desc):
+    """128-bit two's-complement keys as two little-endian words sort like
+    the Python integers they encode."""
+    words = np.array([[(v % (1 << 128)) & ((1 << 64) - 1), (v % (1 << 128)) >> 64] for v in values],
+                     dtype=np.uint64).reshape(-1, 2)
+    want = sorted(range(len(values)), key=lambda i: values[i], reverse=desc)
+    _, got = oracle.sort_wide(words, np.arange(len(values), dtype=np.uint32), key_type="signed", descending=desc)
+    assert got.tolist() == want
