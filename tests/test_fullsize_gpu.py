@@ -205,3 +205,34 @@ def test_c3_segmented_batch_full(gpu):
         a, n = int(offs[j]), int(L[s])
         k = g[a:a + n].cpu().numpy()
         assert np.array_equal(out[a:a + n].cpu().numpy(), oracle.sort(k)), s
+
+
+def test_pairs_beyond_2e32_elements(gpu):
+    """2^32 + 4099 u16 keys with a u64 index payload: positions, counts and
+    offsets pass 2^32 (64-bit throughout).  Checked by the properties that
+    fix a stable sort: non-decreasing keys, the payload a permutation of
+    0..n-1, keys_out[i] == keys_in[vals_out[i]], equal keys in input order."""
+    n = (1 << 32) + 4099
+    ki = fsgen.keys_device("zipf", 16, n, fsgen.seed_for(1, 2) + 1, device=gpu)
+    vi = fsgen.index_device(n, 8, device=gpu)
+    ws = fs.Workspace(gpu)
+    ko, vo = fs.sort_pairs(ki, vi, workspace=ws)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    del vi, ws
+    torch.cuda.empty_cache()
+    seen = torch.zeros(n, dtype=torch.bool, device=gpu)
+    for a in range(0, n, CHUNK):
+        b = min(n, a + CHUNK)
+        idx = vo[a:b].view(torch.int64)
+        assert int(idx.min()) >= 0 and int(idx.max()) < n
+        seen[idx] = True
+        assert torch.equal(bits(ki)[idx], bits(ko)[a:b]), a
+        e = min(n, b + 1)
+        k = as_i64(ko[a:e])
+        v = vo[a:e].view(torch.int64)
+        assert bool((k[1:] >= k[:-1]).all()), a
+        eq = k[1:] == k[:-1]
+        assert bool((v[1:][eq] > v[:-1][eq]).all()), a
+        del idx, k, v, eq
+    assert bool(seen.all())
