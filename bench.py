@@ -138,10 +138,17 @@ def cpu_baseline(keys_dev, vals_dev, key_bits, val_bytes, budget_s=12.0):
                              else oracle.sort_mt(k, v, threads=threads))
     del np
     what = "keys only" if v is None else "with payload"
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": many / 1e9, "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
             "sample": f"first 2^26 keys of the workload ({what}), sorted by the C oracle {repsm}x over "
                       f"{threads} threads ({elm:.1f} s) and {reps1}x on one thread ({el1:.1f} s)",
             "single_thread": {"value": one / 1e9, "unit": "Gkeys/s", "cores": 1},
+            "host_cpu": model, "host_cpus_visible": os.cpu_count(),
             "t_unit_keys_per_s_per_core": {"all_cores": many / threads, "one_core": one}}
 
 
