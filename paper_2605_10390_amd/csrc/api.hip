@@ -163,7 +163,10 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     uint64_t* base = reinterpret_cast<uint64_t*>(w + L.base);
     uint32_t* part = reinterpret_cast<uint32_t*>(w + L.part);
 
-    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(err, 1, 0, s));
+    // every range that must start at zero, cleared by one launch
+    ZeroRanges zero;
+    zero.p[0] = err;
+    zero.words[0] = 1;
 
     if (L.expand16) {
         // the whole key is one 16-bit digit: compressed histogram, prefix,
@@ -171,7 +174,9 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         uint32_t* wrap = reinterpret_cast<uint32_t*>(w + L.wrap);
         uint64_t* h16 = reinterpret_cast<uint64_t*>(w + L.h16);
         uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
+        zero.p[1] = wrap;
+        zero.words[1] = 2ull * kHist16Words;
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_zero(zero, s));
         FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_hist16c(static_cast<const uint16_t*>(keys_in), n, L.hist_groups,
                                                          part, wrap, wrap + kHist16Words, s, (uint32_t)opos,
                                                          (uint32_t)oneg));
@@ -205,7 +210,13 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     a.err = err;
     a.ord_pos = opos;
     a.ord_neg = oneg;
-    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(a.tickets, (uint64_t)L.digits * kXcds * kTicketStride, 0, s));
+    zero.p[1] = a.tickets;
+    zero.words[1] = (uint64_t)L.digits * kXcds * kTicketStride;
+    if (L.pairs16) {
+        zero.p[2] = reinterpret_cast<uint32_t*>(w + L.wrap);
+        zero.words[2] = 2ull * kHist16Words;
+    }
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_zero(zero, s));
     if (L.pairs16) {
         // 16-bit keys with payloads: the first histogram is the compressed
         // 2^16-bin histogram (plus digit-0 tile counts); the last pass moves
@@ -214,7 +225,6 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         uint32_t* wrap = reinterpret_cast<uint32_t*>(w + L.wrap);
         uint64_t* h16 = reinterpret_cast<uint64_t*>(w + L.h16);
         uint64_t* p16 = reinterpret_cast<uint64_t*>(w + L.p16);
-        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(wrap, 2ull * kHist16Words, 0, s));
         FS_LAUNCH(FS_KERNEL_HISTOGRAM, n,
                   launch_tile_hist16(a, L.hist16_groups, part16, wrap, wrap + kHist16Words, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part16, L.hist16_groups, wrap, wrap + kHist16Words, h16, s));
@@ -533,8 +543,12 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
     x.tdesc = reinterpret_cast<SegTileDesc*>(w + o_tdesc);
     x.tmp_k = w + o_tk;
     x.tmp_v = w + o_tv;
-    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.err, 1 + 256, 0, s));
-    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_fill_u32(x.state, (uint64_t)max_tiles * kRadix, 0, s));
+    ZeroRanges zero;
+    zero.p[0] = x.err;
+    zero.words[0] = 1 + 256;
+    zero.p[1] = x.state;
+    zero.words[1] = (uint64_t)max_tiles * kRadix;
+    FS_LAUNCH(FS_KERNEL_AUX, 0, launch_zero(zero, s));
     FS_LAUNCH(FS_KERNEL_SEGMENTED, total_keys, launch_segmented(x, tune, s));
     return FS_OK;
 }

@@ -37,6 +37,12 @@ int device_cu_count();
 
 // ---- launchers (each returns hipGetLastError after enqueueing) ----------
 hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStream_t s);
+// zero up to four word ranges in one launch (ranges with words == 0 are skipped)
+struct ZeroRanges {
+    uint32_t* p[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t words[4] = {0, 0, 0, 0};
+};
+hipError_t launch_zero(const ZeroRanges& r, hipStream_t s);
 
 // pos, neg: key order masks (order_map); 0, 0 counts the keys as they are
 hipError_t launch_hist16c(const uint16_t* keys, uint64_t n, uint32_t groups, uint32_t* part,

@@ -23,6 +23,25 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t words, uint32_t value) {
         p[i] = value;
 }
 
+__global__ void k_zero(ZeroRanges r, uint64_t total) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        uint64_t j = i;
+        int k = 0;
+        while (j >= r.words[k]) j -= r.words[k++];  // total bounds i, so k stays below 4
+        r.p[k][j] = 0;
+    }
+}
+
+hipError_t launch_zero(const ZeroRanges& r, hipStream_t s) {
+    const uint64_t total = r.words[0] + r.words[1] + r.words[2] + r.words[3];
+    if (total == 0) return hipSuccess;
+    uint64_t g = (total + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_zero<<<(unsigned)g, 256, 0, s>>>(r, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStream_t s) {
     if (words == 0) return hipSuccess;
     uint64_t g = (words + 255) / 256;
