@@ -10,6 +10,7 @@ namespace fs {
 
 // Histogram launch shapes.
 constexpr int kHist16Threads = 1024;
+constexpr int kHist16Unroll = 4;  // vectors per thread in flight in k_hist16c
 constexpr int kHist16Words = 32768;  // 2^16 bins as packed 16-bit counter pairs
 constexpr int kHist8Threads = 512;
 

@@ -69,35 +69,52 @@ __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
     const uint64_t v0 = (uint64_t)blockIdx.x * per;
     const uint64_t v1 = v0 + per < nvec ? v0 + per : nvec;
     const u32x4* vec = reinterpret_cast<const u32x4*>(keys + head);
-    for (uint64_t v = v0 + tid; v < v1; v += kHist16Threads) {
-        u32x4 q = __builtin_nontemporal_load(&vec[v]);
-        if constexpr (ORD) q = order_map_vec<uint16_t>(q, opos, oneg);
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-        // whole wave holding one key value: one add for all of it
-        const uint32_t k0 = w[0] & 0xFFFFu;
-        const bool uniform_lane = (w[0] >> 16) == k0 && w[1] == w[0] && w[2] == w[0] && w[3] == w[0];
-        const uint32_t kw = __builtin_amdgcn_readfirstlane(k0);
-        const uint64_t active = ballot(true);
-        const uint64_t same = ballot(uniform_lane && k0 == kw);
-        if (same == active) {
-            if (lanes_below(active) == 0)
-                hist16_add(cnt, kw, 8u * popc64(active), wrap_lo, wrap_word);
-            continue;
-        }
-        // otherwise one add per run of equal keys within the lane (counted
-        // at the run's last key, 0 elsewhere), all issued together
-        uint32_t k[8], c[8];
+    // kHist16Unroll vectors per thread are requested before any is counted,
+    // so each thread keeps that many loads in flight (HBM latency, not the
+    // LDS adds, bounds this loop otherwise)
+    constexpr int U = kHist16Unroll;
+    for (uint64_t v0u = v0 + tid; v0u < v1; v0u += (uint64_t)U * kHist16Threads) {
+        u32x4 qs[U];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) k[e] = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-        uint32_t run = 1;
-#pragma unroll
-        for (int e = 0; e < 7; ++e) {
-            const bool same_next = k[e + 1] == k[e];
-            c[e] = same_next ? 0u : run;
-            run = same_next ? run + 1 : 1u;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t v = v0u + (uint64_t)u * kHist16Threads;
+            qs[u] = __builtin_nontemporal_load(&vec[v < v1 ? v : v0u]);
         }
-        c[7] = run;
-        hist16_add_n<8>(cnt, k, c, wrap_lo, wrap_word);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t v = v0u + (uint64_t)u * kHist16Threads;
+            if (__builtin_amdgcn_readfirstlane((uint32_t)(v >= v1 ? 1u : 0u)) && v >= v1) break;  // wave-uniform tail
+            const bool in = v < v1;
+            u32x4 q = qs[u];
+            if constexpr (ORD) q = order_map_vec<uint16_t>(q, opos, oneg);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+            // whole wave holding one key value: one add for all of it
+            const uint32_t k0 = w[0] & 0xFFFFu;
+            const bool uniform_lane = in && (w[0] >> 16) == k0 && w[1] == w[0] && w[2] == w[0] && w[3] == w[0];
+            const uint32_t kw = __builtin_amdgcn_readfirstlane(k0);
+            const uint64_t active = ballot(in);
+            const uint64_t same = ballot(uniform_lane && k0 == kw);
+            if (same == active) {
+                if (in && lanes_below(active) == 0)
+                    hist16_add(cnt, kw, 8u * popc64(active), wrap_lo, wrap_word);
+                continue;
+            }
+            // otherwise one add per run of equal keys within the lane (counted
+            // at the run's last key, 0 elsewhere), all issued together; lanes
+            // past the end add 0
+            uint32_t k[8], c[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) k[e] = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            uint32_t run = 1;
+#pragma unroll
+            for (int e = 0; e < 7; ++e) {
+                const bool same_next = k[e + 1] == k[e];
+                c[e] = (same_next || !in) ? 0u : run;
+                run = same_next ? run + 1 : 1u;
+            }
+            c[7] = in ? run : 0u;
+            hist16_add_n<8>(cnt, k, c, wrap_lo, wrap_word);
+        }
     }
     // the few keys before the first 16-byte boundary and after the last vector
     if (blockIdx.x == 0) {
