@@ -408,6 +408,25 @@ __device__ __forceinline__ uint32_t value_at(const uint64_t* p, uint32_t lo, uin
 // position i; positions at or past the total are not written.  With ORD
 // the histogram counts mapped keys and each value is unmapped as it is
 // written (order_unmap with masks opos, oneg).
+// value_at over all 2^16 bins by one wave: each round the 64 lanes probe
+// evenly spaced bins and the interval shrinks 64-fold (3 rounds of parallel
+// loads instead of 16 dependent ones).  Every lane returns the result.
+__device__ __forceinline__ uint32_t value_at_wave(const uint64_t* p, uint64_t pos) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t lo = 0, len = 65536;  // the answer is in [lo, lo + len); p[lo] <= pos
+    while (len > 1) {
+        const uint32_t step = (len + 63) / 64;
+        const uint32_t idx = lo + lane * step;
+        const bool ok = idx < lo + len && p[idx] <= pos;
+        const uint64_t m = ballot(ok);  // lane 0 always holds (p[lo] <= pos); ok is monotone in lane
+        const uint32_t last = 63 - (uint32_t)__builtin_clzll(m);
+        lo += last * step;
+        const uint32_t rest = lo + step < 65536u ? step : 65536u - lo;
+        len = rest < len ? rest : len;
+    }
+    return lo;
+}
+
 template <bool kVec, bool ORD>
 __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __restrict__ p16,
                                                              uint16_t* __restrict__ out, uint64_t first,
@@ -418,9 +437,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand16(const uint64_t* __r
     const uint64_t rs = first + (uint64_t)blockIdx.x * kExpandSpan;
     if (rs >= end) return;
     const uint64_t re = rs + kExpandSpan < end ? rs + kExpandSpan : end;
-    if (threadIdx.x == 0) {
-        window[0] = value_at(p16, 0, 65535, rs);
-        window[1] = value_at(p16, 0, 65535, re - 1);
+    // the block's first and last values: wave 0 and wave 1 search at once
+    if (threadIdx.x < 128) {
+        const uint32_t v = value_at_wave(p16, threadIdx.x < 64 ? rs : re - 1);
+        if ((threadIdx.x & 63) == 0) window[threadIdx.x >> 6] = v;
     }
     __syncthreads();
     const uint32_t vlo = window[0], vhi = window[1];
