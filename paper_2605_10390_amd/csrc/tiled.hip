@@ -276,8 +276,9 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
     constexpr int VK = 8;
     constexpr int NW = THREADS / kWave;
     constexpr int SETW = kRadix / 2;
-    constexpr int TPS = kHistVecs * THREADS * VK / TILE;  // tiles per step
-    static_assert(TPS >= 1 && TPS * TILE == kHistVecs * THREADS * VK, "whole tiles per step");
+    constexpr int HV = 2;  // vectors per thread and step (plus one for misalignment)
+    constexpr int TPS = HV * THREADS * VK / TILE;  // tiles per step
+    static_assert(TPS >= 1 && TPS * TILE == HV * THREADS * VK, "whole tiles per step");
     __shared__ uint32_t cnt[kHist16Words];
     __shared__ uint32_t s_t[2][TPS][kHistCopies][SETW];
 
@@ -295,6 +296,23 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
     int par = 0;
     (void)NW;
     __syncthreads();
+    // a step's vectors, loaded one step ahead
+    u32x4 qn[HV + 1];
+    auto load_step = [&](uint64_t t) {
+        const uint64_t l = t * TILE;
+        const uint64_t ht = t + TPS < thi ? t + TPS : thi;
+        const uint64_t h = ht * TILE < a.n ? ht * TILE : a.n;
+        const uint32_t c = (uint32_t)(h - l);
+        const uint32_t s0 = (uint32_t)((l + head) % VK);
+        const uint32_t m = (s0 + c + VK - 1) / VK;
+        const u32x4* g = reinterpret_cast<const u32x4*>(src + (l - s0));
+#pragma unroll
+        for (int r = 0; r <= HV; ++r) {
+            const uint32_t v = tid + r * THREADS;
+            if (v < m) qn[r] = __builtin_nontemporal_load(&g[v]);
+        }
+    };
+    if (tlo < thi) load_step(tlo);
     for (uint64_t t0 = tlo; t0 < thi; t0 += TPS, par ^= 1) {
         const uint64_t lo = t0 * TILE;
         const uint64_t hi_t = t0 + TPS < thi ? t0 + TPS : thi;
@@ -302,22 +320,21 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
         const uint32_t cntk = (uint32_t)(hi - lo);
         const uint32_t sh = (uint32_t)((lo + head) % VK);
         const uint32_t nv = (sh + cntk + VK - 1) / VK;
-        const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - sh));
-        u32x4 q[kHistVecs + 1];
+        u32x4 q[HV + 1];
 #pragma unroll
-        for (int r = 0; r <= kHistVecs; ++r) {
-            const uint32_t v = tid + r * THREADS;
-            if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
-        }
+        for (int r = 0; r <= HV; ++r) q[r] = qn[r];
+        // the next step's vectors are requested now, in flight while this
+        // step is counted
+        if (t0 + TPS < thi) load_step(t0 + TPS);
         if constexpr (ORD) {  // count the mapped keys (order_map)
 #pragma unroll
-            for (int r = 0; r <= kHistVecs; ++r)
+            for (int r = 0; r <= HV; ++r)
                 if (tid + r * THREADS < nv) q[r] = order_map_vec<K>(q[r], a.ord_pos, a.ord_neg);
         }
 #pragma unroll
-        for (int r = 0; r <= kHistVecs; ++r) {
+        for (int r = 0; r <= HV; ++r) {
             const uint32_t v = tid + r * THREADS;
-            if (r == kHistVecs && __builtin_amdgcn_readfirstlane(v) >= nv) break;  // wave-uniform
+            if (r == HV && __builtin_amdgcn_readfirstlane(v) >= nv) break;  // wave-uniform
             if (v < nv) {
                 K k[VK];
                 __builtin_memcpy(k, &q[r], 16);
@@ -472,16 +489,23 @@ __global__ __launch_bounds__(kRadix) void k_block_rel(TiledArgs a, int pass) {
     const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
     const uint64_t b0 = sb * kSuperBlock;
     const uint64_t b1 = b0 + kSuperBlock < blocks ? b0 + kSuperBlock : blocks;
-    constexpr int kBatch = 16;
+    constexpr int kBatch = 64;  // loads in flight per round trip
     uint32_t run = 0;
     for (uint64_t b = b0; b < b1; b += kBatch) {
         uint32_t c[kBatch];
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i) c[i] = b + i < b1 ? a.bsum[(b + i) * kRadix + d] : 0;
+        for (int i = 0; i < kBatch; ++i) {
+            // clamped index: every load is issued unconditionally, so the
+            // whole batch is in flight at once; the clamped ones are unused
+            const uint64_t j = b + i < b1 ? b + i : b1 - 1;
+            c[i] = a.bsum[j * kRadix + d];
+        }
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
-            if (b + i < b1) a.bsum[(b + i) * kRadix + d] = run;
-            run += c[i];
+            if (b + i < b1) {
+                a.bsum[(b + i) * kRadix + d] = run;
+                run += c[i];
+            }
         }
     }
     a.ssum[sb * kRadix + d] = run;
@@ -493,9 +517,21 @@ __global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
     const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
     const uint64_t supers = (blocks + kSuperBlock - 1) / kSuperBlock;
     uint64_t run = a.base[(uint64_t)pass * 2 * kRadix + d];
-    for (uint64_t sb = 0; sb < supers; ++sb) {
-        a.sbase[sb * kRadix + d] = run;
-        run += a.ssum[sb * kRadix + d];
+    constexpr int kBatch = 32;  // loads in flight per round trip
+    for (uint64_t sb0 = 0; sb0 < supers; sb0 += kBatch) {
+        uint32_t c[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const uint64_t j = sb0 + i < supers ? sb0 + i : supers - 1;  // clamped, as above
+            c[i] = a.ssum[j * kRadix + d];
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            if (sb0 + i < supers) {
+                a.sbase[(sb0 + i) * kRadix + d] = run;
+                run += c[i];
+            }
+        }
     }
 }
 
