@@ -310,6 +310,7 @@ template <bool ORD>
 __global__ __launch_bounds__(kWaveThreads) void k_seg_wave(SegCtx x) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t count = x.ctr[ctr_wave()];
+    if (count == 0) return;  // empty bin: skip the shared counter
     for (;;) {
         uint32_t item = 0;
         if (lane == 0) item = atomicAdd(&x.ctr[ctr_wave_taken()], 1u);
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_seg_small(SegCtx x) {
     const int tid = threadIdx.x;
     for (int i = tid; i < kSmallWaves * kRadix; i += kSmallThreads) (&sm.peers[0][0])[i] = 0;
     const uint32_t nsmall = x.ctr[0];
+    if (nsmall == 0) return;  // empty bin: skip the shared counter
     // queue entries are popped one segment ahead so that the pop overlaps the work
     if (tid == 0) sm.next = add_agent(&x.ctr[1], 1u);
     for (;;) {
@@ -740,6 +742,7 @@ __global__ __launch_bounds__(kExpThreads) void k_seg_expand16(SegCtx x) {
     __shared__ ExpandShared sm;
     const int tid = threadIdx.x;
     const uint32_t nmed = x.ctr[ctr_expand_rest()];
+    if (nmed == 0) return;  // empty bin: skip the shared counter
     uint32_t* taken = &x.ctr[ctr_expand_taken()];
     if (tid == 0) sm.next = add_agent(taken, 1u);
     for (;;) {
@@ -1084,6 +1087,9 @@ __global__ __launch_bounds__(THREADS) void k_seg_scatter(SegCtx x, int c, int j)
     __shared__ VS s_vals[kHasVals ? T : 1];
 
     const uint32_t tiles = x.ctr[ctr_tiles(c)];
+    // a class without large segments: leave before the ticket, whose one
+    // counter every workgroup would otherwise hit at once
+    if (tiles == 0) return;
     const uint32_t epoch = (uint32_t)(1 + 8 * c + j) << (kSegCountBits + 2);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int shift = 8 * j;
@@ -1244,6 +1250,7 @@ __global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t cnt = x.ctr[ctr_wg(c)];
+    if (cnt == 0) return;  // no segment of this class: skip the shared counter
     const uint32_t* list = x.wg_list + (uint64_t)c * x.nseg;
     uint32_t* taken = &x.ctr[ctr_wg_taken(c)];
     for (int i = tid; i < W * kRadix; i += THREADS) (&s_peers[0][0])[i] = 0;

@@ -103,16 +103,18 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         const uint32_t nv = (sh + cnt + VK - 1) / VK;
         const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - sh));
         // all of the step's loads first, then the counting
+        // unconditional loads at a clamped index (lanes past the step's last
+        // vector reload it and never count it), so no guard branch makes
+        // the compiler wait for each load before issuing the next
         u32x4 q[kHistVecs + 1];
 #pragma unroll
         for (int r = 0; r <= kHistVecs; ++r) {
             const uint32_t v = tid + r * kTileHistThreads;
-            if (v < nv) q[r] = __builtin_nontemporal_load(&gv[v]);
+            q[r] = __builtin_nontemporal_load(&gv[v < nv ? v : nv - 1]);
         }
         if constexpr (ORD) {  // count the mapped keys (order_map)
 #pragma unroll
-            for (int r = 0; r <= kHistVecs; ++r)
-                if (tid + r * kTileHistThreads < nv) q[r] = order_map_vec<K>(q[r], a.ord_pos, a.ord_neg);
+            for (int r = 0; r <= kHistVecs; ++r) q[r] = order_map_vec<K>(q[r], a.ord_pos, a.ord_neg);
         }
         // skewed digits: is the digit of the wave's first key shared by at
         // least kSkewLanes lanes in the step's first vector?  (wave-uniform;
