@@ -464,6 +464,127 @@ def run_host32(args):
     print(json.dumps(res), flush=True)
 
 
+def _timed_with_kinds(step, steps):
+    """Time `steps` calls of step() between two events on the current stream,
+    with the library's per-kind launch timers on; returns (ms_total, kinds)."""
+    import torch
+    import ctypes
+    import paper_2605_10390_amd as fs
+    L = fs.lib()
+    L.fs_profile_enable(1)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    kernels = {}
+    for name, kid in {"histogram": 0, "plan": 1, "scatter": 2, "expand": 3, "aux": 4}.items():
+        c, k, ms = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+        L.fs_profile_read(kid, ctypes.byref(c), ctypes.byref(k), ctypes.byref(ms))
+        kernels[name] = {"launches": c.value, "keys": k.value, "ms_total": round(ms.value, 4)}
+        if c.value:
+            kernels[name]["ms_avg"] = round(ms.value / c.value, 4)
+    L.fs_profile_enable(0)
+    return t0.elapsed_time(t1), kernels
+
+
+def _scatter_roofline(kernels, steps, bytes_per_launch, passes_per_step):
+    """HBM roofline of the scatter passes: algorithmic bytes of the passes
+    that run over the event-timed scatter time per step."""
+    ms = kernels["scatter"]["ms_total"] / steps
+    achieved = bytes_per_launch * passes_per_step / (ms / 1e3) / 1e9 if ms > 0 else None
+    return {"bound": "hbm", "kernel": "k_tile_scatter", "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
+            "traffic": None}
+
+
+def run_c8(args):
+    """8-bit keys with a u32 index payload: 2^30 pairs, uniform keys (the
+    high byte of the uniform 16-bit recipe).  The whole key is one digit:
+    one tile-histogram read and one scatter pass of 2(1 + 4) bytes per key."""
+    import torch
+    import fsgen
+    import paper_2605_10390_amd as fs
+    dev = torch.device("cuda:0")
+    n = 1 << 30
+    seed = fsgen.seed_for(8, 0)
+    k16 = fsgen.keys_device("uniform", 16, n, seed, device=dev)
+    keys = ((k16.view(torch.int16).to(torch.int32) >> 8) & 0xFF).to(torch.uint8)
+    del k16
+    vals = fsgen.index_device(n, 4, device=dev)
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    ws = fs.Workspace(dev)
+
+    def step():
+        fs.sort_pairs(keys, vals, keys_out=ko, vals_out=vo, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    ms_total, kernels = _timed_with_kinds(step, args.steps)
+    if ws.error_word() != 0:
+        raise SystemExit(f"device error word {ws.error_word():#x}: result invalid")
+    kk = ko.to(torch.int32)
+    assert bool((kk[1:] >= kk[:-1]).all()), "output keys not sorted"
+    assert torch.equal(keys[vo.view(torch.int32).to(torch.int64)], ko), "payload does not index the keys"
+    ms = ms_total / args.steps
+    res = {"metric": "Gkeys/s, 8-bit keys with a 32-bit index payload", "value": round(n / (ms / 1e3) / 1e9, 3),
+           "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8+u32",
+           "data": "synthetic",
+           "config": {"workload": "key-value sort of 2^30 uint8 keys + uint32 index payload, uniform", "n": n,
+                      "key_bits": 8, "val_bytes": 4, "seed": seed, "parallelism": "single GPU"},
+           "roofline": _scatter_roofline(kernels, args.steps, n * 10, 1),
+           "hbm_frac_whole_sort": round(n * 11 / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "algorithmic_bytes_per_key": 11, "kernels": kernels}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(keys, vals, 8, 4)
+    print(json.dumps(res), flush=True)
+
+
+def run_wide128(args):
+    """Keys of two 64-bit words (128 bits), keys only: 2^28 keys of uniform
+    words.  Two rounds, least significant word first; each round gathers one
+    word through the permutation and sorts (word, u32 permutation entry)
+    pairs in 8 passes of 2(8 + 4) bytes per key; the last permutation moves
+    the whole keys."""
+    import torch
+    import fsgen
+    import paper_2605_10390_amd as fs
+    dev = torch.device("cuda:0")
+    n, words = 1 << 28, 2
+    seed = fsgen.seed_for(9, 0)
+    keys = fsgen.keys_device("uniform", 64, n * words, seed, device=dev).view(torch.int64).view(n, words)
+    ko = torch.empty_like(keys)
+    ws = fs.Workspace(dev)
+
+    def step():
+        fs.sort_wide(keys, keys_out=ko, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    ms_total, kernels = _timed_with_kinds(step, args.steps)
+    if ws.error_word() != 0:
+        raise SystemExit(f"device error word {ws.error_word():#x}: result invalid")
+    # sorted as unsigned 128-bit values: (hi, lo) non-decreasing
+    hi = ko[:, 1] ^ (-(1 << 63))
+    lo = ko[:, 0] ^ (-(1 << 63))
+    ok = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] >= lo[:-1]))
+    assert bool(ok.all()), "output keys not sorted"
+    ms = ms_total / args.steps
+    passes = 8 * words
+    res = {"metric": "Gkeys/s, 128-bit keys (two 64-bit words), keys only", "value": round(n / (ms / 1e3) / 1e9, 3),
+           "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64x2",
+           "data": "synthetic",
+           "config": {"workload": "keys-only sort of 2^28 keys of 128 bits (4 GiB), uniform words", "n": n,
+                      "key_words": words, "seed": seed, "parallelism": "single GPU"},
+           "roofline": _scatter_roofline(kernels, args.steps, n * 24, passes), "kernels": kernels}
+    print(json.dumps(res), flush=True)
+
+
 def pmc_summary(fetch_csv, write_csv, kernel, out_path, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
     dispatch) of `bench.py --copy-probe` into HBM bytes per launch of
@@ -501,7 +622,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4", "stream16", "host32"])
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4", "stream16", "host32", "c8", "wide128"])
     ap.add_argument("--jobs", type=int, default=1000, help="served-stream prefix length (c4)")
     ap.add_argument("--dist", default=None,
                     help="c0/c1/c2a/c2b: key distribution (16-bit: uniform gaussian zipf equal presorted "
@@ -533,6 +654,10 @@ def main():
         return run_stream16(args)
     if args.workload == "host32":
         return run_host32(args)
+    if args.workload == "c8":
+        return run_c8(args)
+    if args.workload == "wide128":
+        return run_wide128(args)
 
     import torch
     import ctypes
