@@ -21,7 +21,12 @@ computes one by one:
   * the batched workload (10^5 log-normal segments, u16/u32, about 1.46e9
     keys, built as the benchmark builds it): every segment against
     torch.sort of (segment id, key) over the whole batch, and a sample of
-    segments (the longest ones among them) against the oracle.
+    segments (the longest ones among them) against the oracle;
+  * 2^30 u8 keys with the index payload: the stable-pair properties above,
+    plus the 256 value counts of input and output;
+  * 2^28 keys of 128 bits: the keys-only result equals the keys of the
+    sort with an index payload, and that payload satisfies the stable-pair
+    properties over whole 128-bit keys.
 """
 import numpy as np
 import pytest
@@ -40,6 +45,8 @@ I64_MIN = -(1 << 63)
 def as_i64(t):
     """Unsigned keys as int64 values in the same order (16/32-bit: widened;
     64-bit: sign bit flipped)."""
+    if t.dtype == torch.uint8:
+        return t.to(torch.int64)
     if t.dtype == torch.uint16:
         return t.view(torch.int16).to(torch.int64) & 0xFFFF
     if t.dtype == torch.uint32:
@@ -47,7 +54,7 @@ def as_i64(t):
     return t.view(torch.int64) ^ I64_MIN
 
 
-SIGNED = {torch.uint16: torch.int16, torch.uint32: torch.int32, torch.uint64: torch.int64}
+SIGNED = {torch.uint8: torch.int8, torch.uint16: torch.int16, torch.uint32: torch.int32, torch.uint64: torch.int64}
 
 
 def bits(t):
@@ -236,3 +243,59 @@ def test_pairs_beyond_2e32_elements(gpu):
         assert bool((v[1:][eq] > v[:-1][eq]).all()), a
         del idx, k, v, eq
     assert bool(seen.all())
+
+
+def test_u8_pairs_2e30(gpu):
+    """The 8-bit workload as the benchmark builds it: the high byte of the
+    uniform 16-bit recipe, with the index payload."""
+    n = 1 << 30
+    k16 = fsgen.keys_device("uniform", 16, n, fsgen.seed_for(8, 0), device=gpu)
+    ki = ((k16.view(torch.int16).to(torch.int32) >> 8) & 0xFF).to(torch.uint8)
+    del k16
+    vi = fsgen.index_device(n, 4, device=gpu)
+    ws = fs.Workspace(gpu)
+    ko, vo = fs.sort_pairs(ki, vi, workspace=ws)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    del vi
+    check_stable_pairs(ki, ko, vo)
+    cin = torch.zeros(256, dtype=torch.int64, device=gpu)
+    cout = torch.zeros(256, dtype=torch.int64, device=gpu)
+    for a in range(0, n, CHUNK):
+        for t, c in ((ki, cin), (ko, cout)):
+            vals, cnt = torch.unique(t[a:a + CHUNK].to(torch.int64), return_counts=True)
+            c.index_add_(0, vals, cnt)
+    assert torch.equal(cin, cout)
+
+
+def test_wide128_keys_2e28(gpu):
+    """2^28 keys of two uniform 64-bit words, as the benchmark builds them."""
+    n, words = 1 << 28, 2
+    keys = fsgen.keys_device("uniform", 64, n * words, fsgen.seed_for(9, 0), device=gpu).view(torch.int64)
+    keys = keys.view(n, words)
+    ws = fs.Workspace(gpu)
+    ko = fs.sort_wide(keys, workspace=ws)
+    idx = fsgen.index_device(n, 4, device=gpu)
+    ko2, vo = fs.sort_wide(keys, vals=idx, workspace=ws)
+    torch.cuda.synchronize()
+    assert ws.error_word() == 0
+    del idx
+    assert torch.equal(ko, ko2), "keys-only result differs from the pair sort's keys"
+    del ko2
+    seen = torch.zeros(n, dtype=torch.bool, device=gpu)
+    flat = keys.view(-1)  # word w of key i at 2i + w: rows are gathered as 1-D words
+    for a in range(0, n, CHUNK // 4):
+        b = min(n, a + CHUNK // 4)
+        e = min(n, b + 1)
+        idx = vo[a:b].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        seen[idx] = True
+        for w in range(words):
+            assert torch.equal(flat[idx * words + w], ko[a:b, w].contiguous()), (a, w)
+        hi = ko[a:e, 1] ^ I64_MIN
+        lo = ko[a:e, 0] ^ I64_MIN
+        v = vo[a:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        gt = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))
+        eq = (hi[1:] == hi[:-1]) & (lo[1:] == lo[:-1])
+        assert bool((gt | eq).all()), f"not sorted near {a}"
+        assert bool((v[1:][eq] > v[:-1][eq]).all()), f"equal keys out of input order near {a}"
+    assert bool(seen.all()), "payload is not a permutation"
