@@ -1,6 +1,8 @@
-"""Host-side accounting of bench.py (no GPU): which digits run, and the
-algorithmic bytes each pass and the whole sort must move."""
+"""Host-side checks of bench.py (no GPU): which digits run, the algorithmic
+bytes each pass and the whole sort must move, and the command-line contract
+(one GPU only; every workload selectable)."""
 import os
+import subprocess
 import sys
 
 import numpy as np
@@ -36,3 +38,20 @@ def test_whole_sort_bytes():
     assert bench.algorithmic_bytes_per_key(16, 4, [True, True]) == 2 + 2 * 12
     assert bench.algorithmic_bytes_per_key(32, 4, [True, True, False, False]) == 4 + 2 * 16
     assert bench.algorithmic_bytes_per_key(64, 8, [False] * 8) == 8 + 2 * 16
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """The benchmark measures one GPU: --gpus N > 1 exits (status 2) with a
+    message before touching any device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_new_workloads_are_selectable():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0
+    for w in ("c0", "c1", "c2a", "c2b", "c3", "c4", "c8", "wide128", "stream16", "host32"):
+        assert w in r.stdout, w
