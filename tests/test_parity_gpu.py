@@ -210,3 +210,47 @@ def test_pair_sorts_with_one_active_digit_and_in_a_graph(gpu):
         torch.cuda.synchronize()
         assert np.array_equal(host(ko), ek)
         assert np.array_equal(host(vo), ev)
+
+
+def test_sorts_replay_from_a_captured_graph(gpu):
+    """A 16-bit keys-only sort and a 16-bit pair sort captured into one HIP
+    graph and replayed four times, with other eager sorts and
+    synchronisations between replays; the outputs are overwritten before
+    every replay and each replay's result must equal the oracle's."""
+    n = 3 * (1 << 20) + 77
+    k = fsgen.keys_host("zipf", 16, n, fsgen.seed_for(1, 2) + 7)
+    v = fsgen.vals_host(n, 4)
+    ki, vi = dev(k), dev(v)
+    ek = oracle.sort(k)
+    pk, pv = oracle.sort(k, v)
+    ko, ko2, vo2 = torch.empty_like(ki), torch.empty_like(ki), torch.empty_like(vi)
+    ws1, ws2 = fs.Workspace(gpu), fs.Workspace(gpu)
+    ws1.get(fs.sort_keys_workspace_bytes(n, 16))
+    ws2.get(fs.sort_pairs_workspace_bytes(n, 16, 4))
+
+    def step():
+        fs.sort_keys(ki, out=ko, workspace=ws1)
+        fs.sort_pairs(ki, vi, keys_out=ko2, vals_out=vo2, workspace=ws2)
+
+    side = torch.cuda.Stream(gpu)
+    side.wait_stream(torch.cuda.current_stream(gpu))
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream(gpu).wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    other = dev(fsgen.keys_host("uniform", 16, 100_003, 5))
+    for r in range(4):
+        for t in (ko, ko2, vo2):
+            t.view(torch.uint8).fill_(0xA5)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert ws1.error_word() == 0 and ws2.error_word() == 0, r
+        assert np.array_equal(host(ko), ek), r
+        assert np.array_equal(host(ko2), pk) and np.array_equal(host(vo2), pv), r
+        # eager work of the program between replays
+        fs.sort_keys(other)
+        torch.cuda.synchronize()
