@@ -80,3 +80,14 @@ def test_extended_entry_points_check_arguments_without_a_gpu():
     assert lib.fs_sort16_host(None, None, 10, 64, 8, None, ctypes.byref(size), None, None) == 1
     assert lib.fs_hist16_accumulate(None, 10, 3, None, None, ctypes.byref(size), None) == 1
     assert lib.fs_hist16_accumulate(None, 10, 2, None, None, ctypes.byref(size), None) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the HIP library the binding raises; there is no CPU path."""
+    import paper_2605_10390_amd as fs
+    monkeypatch.setattr(fs, "_lib", None)
+    monkeypatch.setattr(fs, "LIB_PATH", str(tmp_path / "libfsort.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        fs.lib()
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        fs.sort_keys_workspace_bytes(1000, 16)
