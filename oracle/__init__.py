@@ -181,7 +181,10 @@ def _order_columns(keys, key_type):
     negative = np.signbit(f)
     nan = np.isnan(f)
     cls = np.where(nan, np.where(negative, 0, 2), 1)
-    value = np.where(nan, 0.0, f.astype(np.float64))
+    # NaNs are masked before the cast (their order comes from cls and
+    # nan_rank), so no NaN is ever converted
+    value = np.zeros(f.shape, dtype=np.float64)
+    value[~nan] = f[~nan].astype(np.float64)
     zero_sign = np.where((f == 0) & ~negative, 1, 0)
     payload = (keys.astype(np.uint64) & np.uint64((1 << (8 * keys.itemsize - 1)) - 1)).astype(np.int64)
     nan_rank = np.where(nan, np.where(negative, -payload, payload), 0)

@@ -49,7 +49,12 @@
 static uint64_t key_at(const void *keys, uint64_t i, int key_bytes)
 {
     switch (key_bytes) {
+#ifdef ORACLE_PLANT_KEY8_READS_16
+    /* reads an 8-bit key array with a 16-bit stride */
+    case 1: return ((const uint16_t *)keys)[i];
+#else
     case 1: return ((const uint8_t *)keys)[i];
+#endif
     case 2: return ((const uint16_t *)keys)[i];
     case 4: return ((const uint32_t *)keys)[i];
     default: return ((const uint64_t *)keys)[i];
@@ -203,7 +208,12 @@ int oracle_sort(const void *keys_in, void *keys_out, const void *vals_in, void *
             uint64_t d = (key_at(ks, i, key_bytes) >> (8 * j)) & 0xFF;
             uint64_t slot = start[d]++;
             move_elem(kd, slot, ks, i, key_bytes);
+#ifdef ORACLE_PLANT_PAYLOAD_HALF
+            /* moves only the low 4 bytes of an 8-byte payload */
+            if (val_bytes) move_elem(vbuf[1 - cur], slot, vbuf[cur], i, val_bytes == 8 ? 4 : val_bytes);
+#else
             if (val_bytes) move_elem(vbuf[1 - cur], slot, vbuf[cur], i, val_bytes);
+#endif
         }
 #endif
         cur = 1 - cur;

@@ -55,10 +55,10 @@ def test_float_total_order_of_special_values(width):
         assert np.array_equal(oracle.sort_ordered(shuffled, key_type="float", descending=True), want[::-1])
 
 
-@pytest.mark.parametrize("width", [16, 32, 64])
+@pytest.mark.parametrize("width", [8, 16, 32, 64])
 def test_signed_matches_python_sorted(width):
-    dt = {16: np.uint16, 32: np.uint32, 64: np.uint64}[width]
-    sdt = {16: np.int16, 32: np.int32, 64: np.int64}[width]
+    dt = {8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}[width]
+    sdt = {8: np.int8, 16: np.int16, 32: np.int32, 64: np.int64}[width]
     rng = np.random.default_rng(100 + width)
     for n in (0, 1, 7, 500):
         k = rng.integers(0, 1 << 63, size=n, dtype=np.uint64).astype(dt)
@@ -88,9 +88,9 @@ def test_finite_floats_match_numpy_and_python(width):
         assert vo.tolist() == order
 
 
-@pytest.mark.parametrize("width", [16, 32, 64])
+@pytest.mark.parametrize("width", [8, 16, 32, 64])
 def test_unsigned_matches_counting_sort(width):
-    dt = {16: np.uint16, 32: np.uint32, 64: np.uint64}[width]
+    dt = {8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}[width]
     rng = np.random.default_rng(200 + width)
     k = rng.integers(0, 1 << 63, size=5000, dtype=np.uint64).astype(dt)
     k[:1000] = k[1000:2000]
@@ -123,8 +123,20 @@ def _signed_as_unsigned(keys, key_type):
 _REAL_COLUMNS = oracle._order_columns
 
 
+def test_signed_8bit_hand_ordered():
+    """Every int8 value in two's-complement order, from shuffles, in both
+    directions (an 8-bit key has no IEEE format; FLOAT is refused)."""
+    want = np.array(list(range(0x80, 0x100)) + list(range(0, 0x80)), dtype=np.uint8)
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        sh = want[rng.permutation(want.size)]
+        assert np.array_equal(oracle.sort_ordered(sh, key_type="signed"), want)
+        assert np.array_equal(oracle.sort_ordered(sh, key_type="signed", descending=True), want[::-1])
+
+
 def _pins_pass():
     try:
+        test_signed_8bit_hand_ordered()
         for w in (16, 32, 64):
             test_float_total_order_of_special_values(w)
             test_signed_matches_python_sorted(w)

@@ -17,7 +17,8 @@ import oracle
 from oracle import build as oracle_build
 from tests.checks import check_index_pairs, check_keys
 
-DT = {2: np.uint16, 4: np.uint32, 8: np.uint64}
+DT = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+WIDTHS = (1, 2, 4, 8)
 
 
 def _brute_sort(keys):
@@ -31,16 +32,31 @@ def _brute_sort(keys):
 # Each takes a loaded oracle library so the planted-mistake test can run the
 # same pins against a deliberately broken build.
 
+def _alphabets(kb):
+    """Key alphabets that differ in the lowest, a middle and the top digit."""
+    p = 8 * kb
+    if kb == 1:
+        return [[0, 1, 0x80, 0xFF], [0x0F, 0x10, 0x7F, 0x81]]
+    return [
+        [0, 1, 1 << (p - 8), (1 << p) - 1],
+        [0x0100, 0x00FF, 1 << (p // 2), (1 << (p - 1)) | 1],
+    ]
+
+
+def _wide_payload(n):
+    """n distinct 8-byte payloads whose upper 4 bytes all differ and whose
+    lower 4 bytes repeat, so that a payload moved with only its low half
+    (or a 4-byte stride) comes out wrong."""
+    i = np.arange(n, dtype=np.uint64)
+    return ((i + np.uint64(1)) << np.uint64(36)) | (i % np.uint64(3))
+
+
 def pin_exhaustive_tiny(lib):
     """Every sequence of length <= 4 over alphabets that differ in the
-    lowest, a middle and the top digit, for 16/32/64-bit keys."""
-    for kb in (2, 4, 8):
-        p = 8 * kb
-        alphabets = [
-            [0, 1, 1 << (p - 8), (1 << p) - 1],
-            [0x0100, 0x00FF, 1 << (p // 2), (1 << (p - 1)) | 1],
-        ]
-        for alpha in alphabets:
+    lowest, a middle and the top digit, for 8/16/32/64-bit keys, with
+    4-byte index payloads and with 8-byte payloads above 2^32."""
+    for kb in WIDTHS:
+        for alpha in _alphabets(kb):
             for length in range(0, 5):
                 for seq in itertools.product(alpha, repeat=length):
                     keys = np.array(seq, dtype=DT[kb])
@@ -49,12 +65,18 @@ def pin_exhaustive_tiny(lib):
                     exp_k, exp_v = _brute_sort(keys)
                     assert ko.tolist() == exp_k, (kb, seq)
                     assert vo.tolist() == exp_v, (kb, seq)
+                    wide = _wide_payload(length)
+                    ko8, vo8 = oracle.sort(keys, wide, lib=lib)
+                    assert ko8.tolist() == exp_k, (kb, seq)
+                    assert vo8.tolist() == [int(wide[i]) for i in exp_v], (kb, seq)
+                    assert oracle.sort(keys, lib=lib).tolist() == exp_k, (kb, seq)
 
 
 def pin_random_vs_numpy(lib):
-    """Random keys (with heavy duplication) against numpy's stable argsort."""
+    """Random keys (with heavy duplication) against numpy's stable argsort,
+    with 4-byte index payloads and 8-byte payloads above 2^32."""
     rng = np.random.default_rng(1234)
-    for kb in (2, 4, 8):
+    for kb in WIDTHS:
         info = np.iinfo(DT[kb])
         for n in (1, 2, 3, 17, 255, 256, 257, 1000, 4099):
             for spread in ("full", "few"):
@@ -69,6 +91,10 @@ def pin_random_vs_numpy(lib):
                 assert np.array_equal(ko, keys[order]), (kb, n, spread)
                 assert np.array_equal(vo, order.astype(np.uint32)), (kb, n, spread)
                 assert np.array_equal(oracle.sort(keys, lib=lib), keys[order])
+                wide = _wide_payload(n) ^ rng.integers(0, 1 << 32, size=n, dtype=np.uint64)
+                ko8, vo8 = oracle.sort(keys, wide, lib=lib)
+                assert np.array_equal(ko8, keys[order]), (kb, n, spread)
+                assert np.array_equal(vo8, wide[order]), (kb, n, spread)
 
 
 def pin_closed_forms(lib):
@@ -77,8 +103,8 @@ def pin_closed_forms(lib):
     in input order (the closed forms of the presorted and reverse recipes)."""
     for n in (1, 5, 300, 70000):
         idx = np.arange(n, dtype=np.uint32)
-        for kb in (2, 4, 8):
-            eq = np.full(n, 0xBEEF, dtype=DT[kb])
+        for kb in WIDTHS:
+            eq = np.full(n, 0xBEEF if kb > 1 else 0xBE, dtype=DT[kb])
             ko, vo = oracle.sort(eq, idx, lib=lib)
             assert np.array_equal(vo, idx) and np.array_equal(ko, eq)
         pre = ((np.arange(n, dtype=np.uint64) << np.uint64(16)) // np.uint64(n)).astype(np.uint16)
@@ -98,11 +124,12 @@ def pin_histogram(lib):
     """Leaf counters equal numpy.bincount of the digit, for several digit
     positions and widths."""
     rng = np.random.default_rng(7)
-    for kb in (2, 4, 8):
+    for kb in WIDTHS:
         keys = rng.integers(0, int(np.iinfo(DT[kb]).max), size=5000, dtype=DT[kb], endpoint=True)
         keys[:700] = keys[0]  # a heavy bin
         p = 8 * kb
-        for shift, bits in ((0, 8), (8, 8), (p - 8, 8), (0, 16), (p - 16, 16), (3, 5)):
+        shapes = ((0, 8), (3, 5), (1, 7)) if kb == 1 else ((0, 8), (8, 8), (p - 8, 8), (0, 16), (p - 16, 16), (3, 5))
+        for shift, bits in shapes:
             h = oracle.histogram(keys, shift, bits, lib=lib)
             d = ((keys.astype(np.uint64) >> np.uint64(shift)) & np.uint64((1 << bits) - 1)).astype(np.int64)
             assert np.array_equal(h, np.bincount(d, minlength=1 << bits).astype(np.uint64)), (kb, shift, bits)
@@ -179,7 +206,8 @@ def test_checker_rejects_wrong_results():
 
 
 PLANTS = ["ORACLE_PLANT_UNSTABLE", "ORACLE_PLANT_SKIP_TOP_DIGIT",
-          "ORACLE_PLANT_HIST_OFF_BY_ONE", "ORACLE_PLANT_INCLUSIVE_SCAN"]
+          "ORACLE_PLANT_HIST_OFF_BY_ONE", "ORACLE_PLANT_INCLUSIVE_SCAN",
+          "ORACLE_PLANT_PAYLOAD_HALF", "ORACLE_PLANT_KEY8_READS_16"]
 
 
 def _run_pins_against(path):
@@ -215,12 +243,12 @@ def test_planted_mistake_is_caught(plant):
         assert r.returncode != 0, f"no pin caught {plant}: {r.stdout[-500:]}"
 
 
-@pytest.mark.parametrize("key_bytes,val_bytes", [(2, 0), (2, 4), (4, 4), (8, 0), (8, 8)])
+@pytest.mark.parametrize("key_bytes,val_bytes", [(1, 8), (2, 0), (2, 4), (4, 4), (8, 0), (8, 8)])
 def test_threaded_oracle_equals_single_thread(key_bytes, val_bytes):
     """The CPU-baseline timing variant gives the same bytes as the oracle
     for any thread count, including more threads than keys."""
     rng = np.random.default_rng(key_bytes * 10 + val_bytes)
-    kdt = {2: np.uint16, 4: np.uint32, 8: np.uint64}[key_bytes]
+    kdt = DT[key_bytes]
     for n in (0, 1, 5, 1000, 70_001):
         k = rng.integers(0, 1 << 63, size=n, dtype=np.uint64).astype(kdt)
         k[: n // 4] = k[n // 4: 2 * (n // 4)]
