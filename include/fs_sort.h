@@ -56,9 +56,20 @@ typedef enum {
 } fs_status;
 
 /*
- * Key order flags of fs_sort_keys / fs_sort_pairs (the paper sorts p-bit
- * keys of any precision, Section I; these fix how the bits are compared).
- * FS_FLAG_NONE: unsigned integers, ascending.
+ * Flags of fs_sort_keys / fs_sort_pairs.
+ *
+ * FS_FLAG_CLOBBER_INPUT: the caller allows the sort to overwrite keys_in
+ *   (and vals_in): the input arrays then serve as the second buffer of the
+ *   passes, so the workspace holds no temporary copy of the keys and
+ *   payloads (its size, as queried with the same flags, shrinks by about
+ *   n * (key_bits / 8 + val_bytes) bytes).  On return the input arrays hold
+ *   unspecified bytes.  When the number of digits that are not trivial is
+ *   even, the last pass lands in the input arrays and one extra copy moves
+ *   it to the output.  The result itself does not depend on this flag.
+ *
+ * Key order (the paper sorts p-bit keys of any precision, Section I; these
+ * fix how the bits are compared).  No order flag: unsigned integers,
+ * ascending.
  *   FS_FLAG_SIGNED      two's-complement signed integers.
  *   FS_FLAG_FLOAT       IEEE 754 binary16 / binary32 / binary64 (for 16-bit
  *                       keys also bfloat16, ordered by the same rule) in the
@@ -70,22 +81,30 @@ typedef enum {
  *                       (same bits) stay in input order.
  * SIGNED and FLOAT exclude each other, FLOAT needs 16 bits or more; any
  * other bit is FS_ERR_INVALID_ARG.
- * fs_sort_segmented applies the flags to every segment of the call.
+ * fs_sort_segmented applies the order flags to every segment of the call;
+ * it and fs_sort_keys_wide / fs_sort_pairs_wide accept CLOBBER_INPUT and
+ * leave their inputs and workspace sizes as they are.  The stream and
+ * out-of-core calls take order flags only (CLOBBER_INPUT there is
+ * FS_ERR_INVALID_ARG).
  */
 enum {
     FS_FLAG_NONE = 0,
-    FS_FLAG_SIGNED = 1,
-    FS_FLAG_FLOAT = 2,
-    FS_FLAG_DESCENDING = 4
+    FS_FLAG_CLOBBER_INPUT = 1,
+    FS_FLAG_SIGNED = 2,
+    FS_FLAG_FLOAT = 4,
+    FS_FLAG_DESCENDING = 8
 };
 
 /*
  * Stable ascending sort of n unsigned keys (Section II phases; for 16-bit
  * keys the whole sort is the compressed 2^16-bin histogram written out in
  * order, Algorithm 5 with no trailing bits).
- *   keys_in   device, n keys of key_bits bits (8, 16, 32 or 64); not modified.
+ *   keys_in   device, n keys of key_bits bits (8, 16, 32 or 64); not modified
+ *             unless flags has FS_FLAG_CLOBBER_INPUT.
  *   keys_out  device, n keys; must not overlap keys_in.
- *   flags     key order (FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING).
+ *   flags     FS_FLAG_CLOBBER_INPUT and the key order (FS_FLAG_SIGNED,
+ *             FS_FLAG_FLOAT, FS_FLAG_DESCENDING).  The workspace size
+ *             depends on n, key_bits and CLOBBER_INPUT.
  */
 fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_bits,
                        unsigned flags, void *workspace, size_t *workspace_bytes, void *stream);
@@ -97,8 +116,12 @@ fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_
  * paper's index array (sorted position -> arrival position, Section III-G.3).
  *   keys_in/keys_out  device, n keys of key_bits bits (8, 16, 32, 64).
  *   vals_in/vals_out  device, n values of val_bytes bytes (4 or 8).
- * None of the four ranges may overlap another.  flags: key order, as for
- * fs_sort_keys.
+ * None of the four ranges may overlap another.  flags: FS_FLAG_CLOBBER_INPUT
+ * (keys_in and vals_in may then be overwritten) and the key order, as for
+ * fs_sort_keys.  For 16-bit keys the keys of the last pass are never
+ * stored (they are written from the 2^16-bin histogram), so the first pass
+ * uses keys_out as its key buffer and the workspace holds no key copy even
+ * without CLOBBER_INPUT.
  */
 fs_status fs_sort_pairs(const void *keys_in, void *keys_out, const void *vals_in, void *vals_out,
                         uint64_t n, int key_bits, int val_bytes, unsigned flags,

@@ -25,7 +25,7 @@ FS_OK, FS_ERR_INVALID_ARG, FS_ERR_UNSUPPORTED, FS_ERR_WORKSPACE_TOO_SMALL, FS_ER
 _KEY_BITS = {torch.uint8: 8, torch.int8: 8, torch.uint16: 16, torch.int16: 16, torch.uint32: 32, torch.int32: 32,
              torch.uint64: 64, torch.int64: 64, torch.float16: 16, torch.bfloat16: 16,
              torch.float32: 32, torch.float64: 64}
-FS_FLAG_NONE, FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING = 0, 1, 2, 4
+FS_FLAG_NONE, FS_FLAG_CLOBBER_INPUT, FS_FLAG_SIGNED, FS_FLAG_FLOAT, FS_FLAG_DESCENDING = 0, 1, 2, 4, 8
 _TYPE_FLAGS = {"unsigned": FS_FLAG_NONE, "signed": FS_FLAG_SIGNED, "float": FS_FLAG_FLOAT}
 _VAL_BYTES = {torch.uint32: 4, torch.int32: 4, torch.float32: 4, torch.uint64: 8,
               torch.int64: 8, torch.float64: 8}
@@ -149,45 +149,48 @@ class Workspace:
         return int(self.buf[:4].view(torch.int32).item())
 
 
-def sort_keys_workspace_bytes(n, key_bits):
+def sort_keys_workspace_bytes(n, key_bits, flags=FS_FLAG_NONE):
     size = ctypes.c_size_t(0)
-    st = lib().fs_sort_keys(None, None, int(n), int(key_bits), 0, None, ctypes.byref(size), None)
+    st = lib().fs_sort_keys(None, None, int(n), int(key_bits), int(flags), None, ctypes.byref(size), None)
     if st != FS_OK:
         raise FsError(st, "fs_sort_keys (workspace query)")
     return size.value
 
 
-def sort_pairs_workspace_bytes(n, key_bits, val_bytes):
+def sort_pairs_workspace_bytes(n, key_bits, val_bytes, flags=FS_FLAG_NONE):
     size = ctypes.c_size_t(0)
-    st = lib().fs_sort_pairs(None, None, None, None, int(n), int(key_bits), int(val_bytes), 0,
+    st = lib().fs_sort_pairs(None, None, None, None, int(n), int(key_bits), int(val_bytes), int(flags),
                              None, ctypes.byref(size), None)
     if st != FS_OK:
         raise FsError(st, "fs_sort_pairs (workspace query)")
     return size.value
 
 
-def sort_keys(keys, out=None, workspace=None, key_type=None, descending=False):
-    """Stable sort of a 1-D key tensor (returns `out`); order per order_flags."""
+def sort_keys(keys, out=None, workspace=None, key_type=None, descending=False, clobber=False):
+    """Stable sort of a 1-D key tensor (returns `out`); order per order_flags.
+    clobber=True lets the sort overwrite `keys` (FS_FLAG_CLOBBER_INPUT: no
+    temporary copy in the workspace)."""
     _check_dev(keys)
     bits = _key_bits(keys)
     n = keys.numel()
     if out is None:
         out = torch.empty_like(keys)
     _check_dev(out)
+    flags = order_flags(keys, key_type, descending) | (FS_FLAG_CLOBBER_INPUT if clobber else 0)
     ws = workspace or Workspace(keys.device)
-    need = sort_keys_workspace_bytes(n, bits)
+    need = sort_keys_workspace_bytes(n, bits, flags)
     buf = ws.get(need)
     size = ctypes.c_size_t(buf.numel())
-    st = lib().fs_sort_keys(_ptr(keys), _ptr(out), n, bits, order_flags(keys, key_type, descending),
-                            _ptr(buf), ctypes.byref(size), _stream(keys))
+    st = lib().fs_sort_keys(_ptr(keys), _ptr(out), n, bits, flags, _ptr(buf), ctypes.byref(size), _stream(keys))
     if st != FS_OK:
         raise FsError(st, "fs_sort_keys")
     return out
 
 
 def sort_pairs(keys, vals, keys_out=None, vals_out=None, workspace=None, key_type=None,
-               descending=False):
-    """Stable sort of (key, value) pairs; returns (keys, values); order per order_flags."""
+               descending=False, clobber=False):
+    """Stable sort of (key, value) pairs; returns (keys, values); order per
+    order_flags.  clobber=True lets the sort overwrite `keys` and `vals`."""
     _check_dev(keys, vals)
     bits = _key_bits(keys)
     if vals.dtype not in _VAL_BYTES:
@@ -199,12 +202,12 @@ def sort_pairs(keys, vals, keys_out=None, vals_out=None, workspace=None, key_typ
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     _check_dev(keys_out, vals_out)
+    flags = order_flags(keys, key_type, descending) | (FS_FLAG_CLOBBER_INPUT if clobber else 0)
     ws = workspace or Workspace(keys.device)
-    buf = ws.get(sort_pairs_workspace_bytes(n, bits, vb))
+    buf = ws.get(sort_pairs_workspace_bytes(n, bits, vb, flags))
     size = ctypes.c_size_t(buf.numel())
     st = lib().fs_sort_pairs(_ptr(keys), _ptr(keys_out), _ptr(vals), _ptr(vals_out), n, bits, vb,
-                             order_flags(keys, key_type, descending), _ptr(buf), ctypes.byref(size),
-                             _stream(keys))
+                             flags, _ptr(buf), ctypes.byref(size), _stream(keys))
     if st != FS_OK:
         raise FsError(st, "fs_sort_pairs")
     return keys_out, vals_out

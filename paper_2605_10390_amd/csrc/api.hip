@@ -21,7 +21,7 @@ int device_cu_count() {
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
+SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus, bool clobber) {
     SortLayout L;
     L.key_bytes = key_bytes;
     L.val_bytes = val_bytes;
@@ -75,8 +75,12 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus) {
             L.h16 = take(8ull * 65536);
             L.p16 = take(8ull * 65537);
         }
-        L.tmp_keys = take((size_t)n * key_bytes);
-        if (val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
+        // the passes' second buffer: none with clobber (the input serves);
+        // a 16-bit pair sort's keys use the output (the last pass stores no
+        // keys, they are expanded from the histogram afterwards)
+        L.clobber = clobber;
+        if (!clobber && !L.pairs16) L.tmp_keys = take((size_t)n * key_bytes);
+        if (!clobber && val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
     }
     L.total = off;
     return L;
@@ -100,7 +104,8 @@ constexpr uint64_t kMaxKeys = 1ull << 36;
 #define FS_LAUNCH(kind, keys, expr) FS_TRY(timed((kind), (keys), s, [&]() { return (expr); }))
 
 // Key order masks of order_map (fs_device.hpp) for the order flags; false
-// for an unknown flag or SIGNED together with FLOAT.
+// for an unknown flag (FS_FLAG_CLOBBER_INPUT included: callers that accept
+// it strip it first) or SIGNED together with FLOAT.
 bool order_masks(unsigned flags, int key_bits, uint64_t* pos, uint64_t* neg) {
     const unsigned known = FS_FLAG_SIGNED | FS_FLAG_FLOAT | FS_FLAG_DESCENDING;
     if ((flags & ~known) || ((flags & FS_FLAG_SIGNED) && (flags & FS_FLAG_FLOAT))) return false;
@@ -127,11 +132,12 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
                            size_t* workspace_bytes, hipStream_t s) {
     if (key_bits != 8 && key_bits != 16 && key_bits != 32 && key_bits != 64) return FS_ERR_INVALID_ARG;
     uint64_t opos = 0, oneg = 0;
-    if (!order_masks(flags, key_bits, &opos, &oneg)) return FS_ERR_INVALID_ARG;
+    const bool clobber = (flags & FS_FLAG_CLOBBER_INPUT) != 0;
+    if (!order_masks(flags & ~(unsigned)FS_FLAG_CLOBBER_INPUT, key_bits, &opos, &oneg)) return FS_ERR_INVALID_ARG;
     if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
     if (!workspace_bytes || n > kMaxKeys) return FS_ERR_INVALID_ARG;
     const int kb = key_bits / 8;
-    const SortLayout L = sort_layout(n, kb, val_bytes, device_cu_count());
+    const SortLayout L = sort_layout(n, kb, val_bytes, device_cu_count(), clobber);
     if (!workspace) {
         *workspace_bytes = L.total;
         return FS_OK;
@@ -190,10 +196,12 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     TiledArgs a;
     a.in_k = keys_in;
     a.out_k = keys_out;
-    a.tmp_k = w + L.tmp_keys;
+    // the passes' second buffer (finish_plan's kBufTmp): the input itself
+    // with clobber, the output for the keys of a 16-bit pair sort
+    a.tmp_k = L.clobber ? const_cast<void*>(keys_in) : L.pairs16 ? keys_out : static_cast<void*>(w + L.tmp_keys);
     a.in_v = vals_in;
     a.out_v = vals_out;
-    a.tmp_v = val_bytes ? w + L.tmp_vals : nullptr;
+    a.tmp_v = !val_bytes ? nullptr : L.clobber ? const_cast<void*>(vals_in) : static_cast<void*>(w + L.tmp_vals);
     a.n = n;
     a.tiles = L.tiles;
     a.tile = L.tile;
@@ -228,7 +236,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         FS_LAUNCH(FS_KERNEL_HISTOGRAM, n,
                   launch_tile_hist16(a, L.hist16_groups, part16, wrap, wrap + kHist16Words, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part16, L.hist16_groups, wrap, wrap + kHist16Words, h16, s));
-        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s, L.clobber));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
         for (int j = 0; j < 2; ++j) {
             if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
@@ -242,7 +250,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         return FS_OK;
     }
     FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
-    FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s));
+    FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s, L.clobber));
     for (int j = 0; j < L.digits; ++j) {
         if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
@@ -268,11 +276,13 @@ static fs_status sort_wide_impl(const void* keys_in, void* keys_out, const void*
     if (words < 1 || words > kMaxKeyWords) return FS_ERR_INVALID_ARG;
     if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return FS_ERR_INVALID_ARG;
     if (!workspace_bytes || n > kMaxKeys) return FS_ERR_INVALID_ARG;
-    if (words == 1)  // one word is a 64-bit key
-        return sort_impl(keys_in, keys_out, vals_in, vals_out, n, 64, val_bytes, flags, workspace,
-                         workspace_bytes, s);
+    if (words == 1)  // one word is a 64-bit key (inputs left as they are)
+        return sort_impl(keys_in, keys_out, vals_in, vals_out, n, 64, val_bytes,
+                         flags & ~(unsigned)FS_FLAG_CLOBBER_INPUT, workspace, workspace_bytes, s);
     // order masks per word: the top word carries the sign; a float's other
     // words are complemented when it is negative
+    // the inputs are only gathered from, so CLOBBER_INPUT changes nothing
+    flags &= ~(unsigned)FS_FLAG_CLOBBER_INPUT;
     const unsigned known = FS_FLAG_SIGNED | FS_FLAG_FLOAT | FS_FLAG_DESCENDING;
     if ((flags & ~known) || ((flags & FS_FLAG_SIGNED) && (flags & FS_FLAG_FLOAT))) return FS_ERR_INVALID_ARG;
     const uint64_t sign = 1ull << 63;
@@ -464,6 +474,9 @@ fs_status fs_sort_segmented_tuned(const fs_segment* d_segments, uint32_t num_seg
                                   void* workspace, size_t* workspace_bytes, void* stream) {
     using namespace fs;
     if (!workspace_bytes) return FS_ERR_INVALID_ARG;
+    // CLOBBER_INPUT is accepted and changes nothing (segments have their
+    // own temporary pools)
+    flags &= ~(unsigned)FS_FLAG_CLOBBER_INPUT;
     uint64_t opos[3], oneg[3];  // key order masks per width (16, 32, 64 bits)
     for (int w = 0; w < 3; ++w)
         if (!order_masks(flags, 16 << w, &opos[w], &oneg[w])) return FS_ERR_INVALID_ARG;

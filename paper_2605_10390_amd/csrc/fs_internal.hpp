@@ -25,6 +25,7 @@ struct SortLayout {
     int key_bytes = 0, val_bytes = 0, digits = 0;
     bool expand16 = false;  // 16-bit keys only: compressed histogram + expansion
     bool pairs16 = false;   // 16-bit keys + payload: tiled passes, keys expanded at the end
+    bool clobber = false;   // the input arrays are the passes' second buffer
     uint32_t hist_groups = 0;  // workgroups of the histogram kernel
     uint32_t hist16_groups = 0;
     uint32_t tile = 0, scatter_groups = 0;
@@ -33,7 +34,8 @@ struct SortLayout {
            ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, part16 = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
 };
 
-SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus);
+// clobber: the input arrays are the passes' second buffer (no temporary copy)
+SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus, bool clobber = false);
 int device_cu_count();
 
 // ---- launchers (each returns hipGetLastError after enqueueing) ----------
@@ -54,7 +56,7 @@ hipError_t launch_merge16(const uint32_t* part, uint32_t groups, const uint32_t*
                           bool accumulate = false);
 hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s);
 hipError_t launch_plan_from16(const uint64_t* h16, uint64_t n, uint64_t* hist, uint64_t* base,
-                              uint32_t* plan, hipStream_t s);
+                              uint32_t* plan, hipStream_t s, bool clobber = false);
 hipError_t launch_hist8(const void* keys, uint64_t n, int key_bytes, uint32_t groups,
                         uint32_t* part, hipStream_t s);
 hipError_t launch_plan8(const uint32_t* part, uint32_t groups, int digits, uint64_t n,
@@ -103,7 +105,7 @@ int tiled_scatter_per_cu(int key_bytes, int val_bytes);
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s);
 hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s);
 hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
-                            uint64_t* base, uint32_t* plan, hipStream_t s);
+                            uint64_t* base, uint32_t* plan, hipStream_t s, bool clobber = false);
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
                                bool skip_keys, hipStream_t s);
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,

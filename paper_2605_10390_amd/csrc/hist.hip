@@ -261,19 +261,20 @@ hipError_t launch_scan16(const uint64_t* h16, uint64_t* p16, hipStream_t s) {
 // Digit histograms of 16-bit keys as marginals of the 2^16-bin histogram:
 // digit 0 (low byte) sums each column, digit 1 (high byte) each row.
 __global__ __launch_bounds__(256) void k_plan_from16(const uint64_t* __restrict__ h16, uint64_t n,
-                                                     uint64_t* hist, uint64_t* base, uint32_t* plan) {
+                                                     uint64_t* hist, uint64_t* base, uint32_t* plan,
+                                                     bool clobber) {
     const int b = threadIdx.x;
     uint64_t h[2] = {0, 0};
     for (int i = 0; i < 256; ++i) {
         h[0] += h16[i * 256 + b];
         h[1] += h16[b * 256 + i];
     }
-    finish_plan(h, 2, n, hist, base, plan);
+    finish_plan(h, 2, n, hist, base, plan, clobber);
 }
 
 hipError_t launch_plan_from16(const uint64_t* h16, uint64_t n, uint64_t* hist, uint64_t* base,
-                              uint32_t* plan, hipStream_t s) {
-    k_plan_from16<<<1, 256, 0, s>>>(h16, n, hist, base, plan);
+                              uint32_t* plan, hipStream_t s, bool clobber) {
+    k_plan_from16<<<1, 256, 0, s>>>(h16, n, hist, base, plan, clobber);
     return hipGetLastError();
 }
 

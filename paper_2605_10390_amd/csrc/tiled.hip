@@ -436,7 +436,7 @@ constexpr int kPlanThreads = 1024;
 
 __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(const uint32_t* __restrict__ part, uint32_t groups,
                                                             int digits, uint64_t n, uint64_t* hist,
-                                                            uint64_t* base, uint32_t* plan) {
+                                                            uint64_t* base, uint32_t* plan, bool clobber) {
     constexpr int Q = kPlanThreads / kRadix;
     __shared__ uint64_t s_h[Q][kRadix];
     const int tid = threadIdx.x, b = tid % kRadix, q = tid / kRadix;
@@ -463,12 +463,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(const uint32_t* __re
         }
         __syncthreads();
     }
-    finish_plan(h, digits, n, hist, base, plan);
+    finish_plan(h, digits, n, hist, base, plan, clobber);
 }
 
 hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
-                            uint64_t* base, uint32_t* plan, hipStream_t s) {
-    k_tile_plan<<<1, kPlanThreads, 0, s>>>(part, groups, digits, n, hist, base, plan);
+                            uint64_t* base, uint32_t* plan, hipStream_t s, bool clobber) {
+    k_tile_plan<<<1, kPlanThreads, 0, s>>>(part, groups, digits, n, hist, base, plan, clobber);
     return hipGetLastError();
 }
 

@@ -62,6 +62,44 @@ def test_pairs_match_oracle(gpu, bits, vb):
             assert np.array_equal(host(vo), ev), (bits, vb, n, dist)
 
 
+def _clobber_keys(bits, dist, n, seed):
+    if bits == 8:
+        rng = np.random.default_rng(seed)
+        if dist == "equal":
+            return np.full(n, 0x5A, dtype=np.uint8)
+        return rng.integers(0, 256, size=n, dtype=np.uint8)
+    if bits == 16 or dist in fsgen.DISTS_WIDE:
+        return fsgen.keys_host(dist, bits, n, seed)
+    # all-equal wide keys: every digit trivial
+    return np.full(n, 0x1234567890ABCDEF & ((1 << bits) - 1), dtype=fsgen.key_dtype(bits))
+
+
+@pytest.mark.parametrize("bits", [8, 16, 32, 64])
+@pytest.mark.parametrize("vb", [0, 4, 8])
+def test_clobber_input_matches_oracle(gpu, bits, vb):
+    """FS_FLAG_CLOBBER_INPUT: the input arrays are the passes' second
+    buffer.  Odd and even numbers of active digits (an even number ends in
+    the input and is copied out), all-trivial inputs (a copy) and ragged
+    sizes all give the oracle's bytes."""
+    ws = fs.Workspace(gpu)
+    dists = ("uniform", "equal", "presorted") if bits in (8, 16) else ("uniform", "small20", "hot90", "equal")
+    for n in (1, 4097, 3 * 4096 + 17, (1 << 18) + 5):
+        for di, dist in enumerate(dists):
+            seed = fsgen.seed_for(7, di) + n
+            k = _clobber_keys(bits, dist, n, seed)
+            if vb:
+                v = _vals(n, vb, seed)
+                ko, vo = fs.sort_pairs(dev(k), dev(v), workspace=ws, clobber=True)
+                ek, ev = oracle.sort(k, v)
+                assert np.array_equal(host(vo), ev), (bits, vb, n, dist)
+            else:
+                ko = fs.sort_keys(dev(k), workspace=ws, clobber=True)
+                ek = oracle.sort(k)
+            torch.cuda.synchronize()
+            assert ws.error_word() == 0
+            assert np.array_equal(host(ko), ek), (bits, vb, n, dist)
+
+
 def test_index_payload_is_stable_permutation(gpu):
     """The configs' payload (original index): invariants pin the result."""
     n = 5 * 4096 + 3
