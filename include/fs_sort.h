@@ -110,6 +110,35 @@ fs_status fs_sort_keys(const void *keys_in, void *keys_out, uint64_t n, int key_
                        unsigned flags, void *workspace, size_t *workspace_bytes, void *stream);
 
 /*
+ * fs_sort_keys for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same sort, bit for bit, with the workspace taken from a static device
+ * array of FS_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library instead of
+ * from the caller.  Each GPU the library runs on holds its own copy of that
+ * array from the first call on it until the process ends; the call makes
+ * no hipMalloc, hipFree or other allocation.
+ *   keys_in, keys_out, n, key_bits, flags  as for fs_sort_keys (the call
+ *             stays asynchronous on `stream`, whose device must be current).
+ *   err_out   NULL, or a device word that receives the call's error word
+ *             (stream-ordered, after the sort; 0 = ok, otherwise the bits
+ *             fs_sort_keys leaves in word 0 of its workspace).
+ * Returns FS_ERR_WORKSPACE_TOO_SMALL, launching nothing, when the workspace
+ * fs_sort_keys would query for (n, key_bits, flags) exceeds
+ * FS_NOALLOC_SCRATCH_BYTES: 16-bit keys take about 34 MiB at any n; 32- and
+ * 64-bit keys with FS_FLAG_CLOBBER_INPUT fit up to about 2^28 keys, without
+ * it up to about 2^23 (32-bit) or 2^22 (64-bit) keys.  Other errors as for
+ * fs_sort_keys.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * there; each call clears what must start at zero.  Calls that overlap in
+ * time on one GPU (on different streams, or from different threads without
+ * stream ordering between them) race on the array and give undefined
+ * results: serialise them, or use fs_sort_keys with workspaces of their own.
+ */
+#define FS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+fs_status fs_sort_keys_noalloc(const void *keys_in, void *keys_out, uint64_t n, int key_bits,
+                               unsigned flags, uint32_t *err_out, void *stream);
+
+/*
  * Stable ascending sort of n (key, value) pairs: keys_out is keys_in in
  * ascending order and vals_out[i] is the value that came with keys_out[i];
  * equal keys keep their input order.  With vals_in[i] = i, vals_out is the

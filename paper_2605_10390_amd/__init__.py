@@ -52,6 +52,8 @@ def lib():
     sz = ctypes.POINTER(ctypes.c_size_t)
     L.fs_sort_keys.argtypes = [vp, vp, u64, i32, ctypes.c_uint, vp, sz, vp]
     L.fs_sort_keys.restype = i32
+    L.fs_sort_keys_noalloc.argtypes = [vp, vp, u64, i32, ctypes.c_uint, vp, vp]
+    L.fs_sort_keys_noalloc.restype = i32
     L.fs_sort_pairs.argtypes = [vp, vp, vp, vp, u64, i32, i32, ctypes.c_uint, vp, sz, vp]
     L.fs_sort_pairs.restype = i32
     L.fs_digit_histograms.argtypes = [vp, u64, i32, i32, vp, vp, sz, vp]
@@ -184,6 +186,29 @@ def sort_keys(keys, out=None, workspace=None, key_type=None, descending=False, c
     st = lib().fs_sort_keys(_ptr(keys), _ptr(out), n, bits, flags, _ptr(buf), ctypes.byref(size), _stream(keys))
     if st != FS_OK:
         raise FsError(st, "fs_sort_keys")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # FS_NOALLOC_SCRATCH_BYTES
+
+
+def sort_keys_noalloc(keys, out, err_out=None, key_type=None, descending=False, clobber=False):
+    """sort_keys through fs_sort_keys_noalloc: the library's static per-GPU
+    scratch array is the workspace, so the call allocates nothing (the
+    caller passes `out`, and optionally `err_out`, a one-element int32/uint32
+    device tensor that receives the call's error word).  Calls that overlap
+    on one GPU race on that array."""
+    _check_dev(keys, out)
+    if err_out is not None:
+        _check_dev(err_out)
+        if err_out.element_size() != 4 or err_out.numel() < 1:
+            raise ValueError("err_out must hold one 32-bit word")
+    bits = _key_bits(keys)
+    flags = order_flags(keys, key_type, descending) | (FS_FLAG_CLOBBER_INPUT if clobber else 0)
+    st = lib().fs_sort_keys_noalloc(_ptr(keys), _ptr(out), keys.numel(), bits, flags,
+                                    _ptr(err_out), _stream(keys))
+    if st != FS_OK:
+        raise FsError(st, "fs_sort_keys_noalloc")
     return out
 
 

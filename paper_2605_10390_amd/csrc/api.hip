@@ -261,6 +261,59 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     return FS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free sorts (fs_sort_keys_noalloc): the workspace is `scratch`,
+// a file-scope device array of FS_NOALLOC_SCRATCH_BYTES that every GPU the
+// library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): each
+// device's address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is handed on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The current device's copy of `scratch` (looked up on first use).
+static fs_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return FS_ERR_DEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return FS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FS_ERR_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FS_OK;
+}
+
+static fs_status sort_keys_noalloc_impl(const void* keys_in, void* keys_out, uint64_t n, int key_bits,
+                                        unsigned flags, uint32_t* err_out, hipStream_t s) {
+    size_t need = 0;
+    fs_status st = sort_impl(nullptr, nullptr, nullptr, nullptr, n, key_bits, 0, flags, nullptr, &need, s);
+    if (st != FS_OK) return st;
+    if (need > (size_t)FS_NOALLOC_SCRATCH_BYTES) return FS_ERR_WORKSPACE_TOO_SMALL;
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != FS_OK) return st;
+    size_t have = FS_NOALLOC_SCRATCH_BYTES;
+    {
+        const ProfileSuspend quiet;  // no timing events: they would be created on demand
+        st = sort_impl(keys_in, keys_out, nullptr, nullptr, n, key_bits, 0, flags, ws, &have, s);
+    }
+    if (st != FS_OK || !err_out) return st;
+    // word 0 of the workspace is the call's error word (0 for n == 0: the
+    // word is then copied as the last call left it, so clear it first)
+    if (n == 0) FS_TRY(launch_fill_u32(static_cast<uint32_t*>(ws), 1, 0, s));
+    FS_TRY(hipMemcpyAsync(err_out, ws, 4, hipMemcpyDeviceToDevice, s));
+    return FS_OK;
+}
+
 // Keys of `words` 64-bit words (word 0 least significant), sorted least
 // significant word first: each round gathers one word of every key through
 // the current permutation (mapped into the requested order) and stably sorts
@@ -360,6 +413,12 @@ fs_status fs_sort_keys(const void* keys_in, void* keys_out, uint64_t n, int key_
                        void* workspace, size_t* workspace_bytes, void* stream) {
     return fs::sort_impl(keys_in, keys_out, nullptr, nullptr, n, key_bits, 0, flags, workspace,
                          workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+fs_status fs_sort_keys_noalloc(const void* keys_in, void* keys_out, uint64_t n, int key_bits, unsigned flags,
+                               uint32_t* err_out, void* stream) {
+    return fs::sort_keys_noalloc_impl(keys_in, keys_out, n, key_bits, flags, err_out,
+                                      static_cast<hipStream_t>(stream));
 }
 
 fs_status fs_sort_pairs(const void* keys_in, void* keys_out, const void* vals_in, void* vals_out,

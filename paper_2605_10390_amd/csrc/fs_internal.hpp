@@ -129,6 +129,13 @@ hipError_t launch_gather_vals(const void* vals_in, void* vals_out, int val_bytes
 
 // ---- per-kernel event timing (include/fs_profile.h) ------------------------
 void profile_mark(int kind, uint64_t keys, hipStream_t s, hipEvent_t* begin_out);
+// While one exists on a thread, that thread's launches record no events.
+struct ProfileSuspend {
+    ProfileSuspend();
+    ~ProfileSuspend();
+    ProfileSuspend(const ProfileSuspend&) = delete;
+    ProfileSuspend& operator=(const ProfileSuspend&) = delete;
+};
 void profile_close(int kind, uint64_t keys, hipStream_t s, hipEvent_t begin);
 
 // Enqueue one launch, bracketed by timing events while profiling is on.

@@ -17,6 +17,9 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Record> g_records;
 std::vector<hipEvent_t> g_pool;
+// calls on this thread that must not create events (the allocation-free
+// entry point) hold a ProfileSuspend
+thread_local int g_suspended = 0;
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -43,9 +46,12 @@ bool profiling() {
     return g_on;
 }
 
+ProfileSuspend::ProfileSuspend() { ++g_suspended; }
+ProfileSuspend::~ProfileSuspend() { --g_suspended; }
+
 void profile_mark(int kind, uint64_t keys, hipStream_t s, hipEvent_t* begin_out) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on) {
+    if (!g_on || g_suspended) {
         *begin_out = nullptr;
         return;
     }

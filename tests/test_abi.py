@@ -147,3 +147,35 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         fs.lib()
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         fs.sort_keys_workspace_bytes(1000, 16)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfsort.so not built")
+def test_noalloc_limits_need_no_gpu():
+    """fs_sort_keys_noalloc refuses, before any device call, every (n, width,
+    flags) whose fs_sort_keys workspace exceeds the static scratch array, and
+    bad arguments as fs_sort_keys does."""
+    lib = ctypes.CDLL(LIB)
+    vp, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)
+    lib.fs_sort_keys.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint, vp, sz, vp]
+    lib.fs_sort_keys_noalloc.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint, vp, vp]
+    text = open(os.path.join(ROOT, "include", "fs_sort.h")).read()
+    m = re.search(r"#define\s+FS_NOALLOC_SCRATCH_BYTES\s+\((\d+)ull\s*<<\s*(\d+)\)", text)
+    cap = int(m.group(1)) << int(m.group(2))
+    assert cap == 64 << 20
+
+    def need(n, bits, flags):
+        size = ctypes.c_size_t(0)
+        assert lib.fs_sort_keys(None, None, n, bits, flags, None, ctypes.byref(size), None) == 0
+        return size.value
+
+    cases = [(1 << 30, 32, 1), (1 << 29, 64, 1), (1 << 24, 32, 0), (1 << 23, 64, 0)]
+    for n, bits, flags in cases:
+        assert need(n, bits, flags) > cap
+        assert lib.fs_sort_keys_noalloc(None, None, n, bits, flags, None, None) == 3
+    # sizes that fit are documented in the header: 16-bit keys at any n,
+    # clobbered 32/64-bit keys to 2^28, others to 2^23 / 2^22
+    for n, bits, flags in [(1 << 36, 16, 0), (1 << 36, 16, 1), (1 << 28, 32, 1), (1 << 28, 64, 1),
+                           (1 << 23, 32, 0), (1 << 22, 64, 0)]:
+        assert need(n, bits, flags) <= cap, (n, bits, flags)
+    assert lib.fs_sort_keys_noalloc(None, None, 10, 24, 0, None, None) == 1
+    assert lib.fs_sort_keys_noalloc(None, None, 10, 16, 6, None, None) == 1
