@@ -22,8 +22,12 @@ Each function follows a passage of the paper (arXiv 2605.10390):
                      integers, IEEE 754 totalOrder of floats, descending
                      (the paper's keys of any precision, Sec. I); written
                      from those orders' definitions, not from a bit mapping
+  partitioned.partitioned_sort -- the sort of an input too large for one
+                     oracle sort, cut in key order into value ranges from
+                     16-bit digit histograms and sorted range by range
 Every function is pinned by tests/test_oracle_pins.py against brute force,
-closed forms and library routines; none is "parity unpinned".
+closed forms and library routines (the partitioned sort by
+tests/test_oracle_partitioned.py); none is "parity unpinned".
 """
 import ctypes
 import os

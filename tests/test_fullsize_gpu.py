@@ -11,10 +11,10 @@ computes one by one:
     together these define the stable sort exactly;
   * 16-bit keys only (2^28): non-decreasing, and the 2^16 value counts equal
     those of the input (for 16-bit keys that is the whole multiset);
-  * 64-bit keys only (2^32): non-decreasing, exact counts of the top and of
-    the bottom 16 bits equal those of the input, and sampled positions hold
-    the order statistic their rank fixes (#{keys < v} <= i < #{keys <= v},
-    counted over the input);
+  * 64-bit keys only (2^32): every output key against the partitioned
+    oracle (oracle.partitioned): the input is cut in key order into ranges
+    of at most 2^28 keys, each sorted by the oracle's counting sort and
+    compared with the output at the offset its key counts fix;
   * sampled positions of the 16-bit sorts against oracle.select over the
     oracle's histogram of the input, and their payloads against the input
     position of that key's occurrence;
@@ -34,6 +34,7 @@ import torch
 
 import fsgen
 import oracle
+from oracle.partitioned import partitioned_sort
 import paper_2605_10390_amd as fs
 
 pytestmark = pytest.mark.gpu
@@ -169,6 +170,10 @@ def test_c2_u32_pairs_2e31(gpu, dist):
 
 @pytest.mark.parametrize("dist", fsgen.DISTS_WIDE)
 def test_c2_u64_keys_2e32(gpu, dist):
+    """Every one of the 2^32 output keys against the partitioned oracle:
+    the input is cut in key order into ranges of at most 2^28 keys (16-bit
+    windows, split again where one bin is larger), each range sorted by
+    oracle.sort and compared with the output at its offset."""
     n = 1 << 32
     ki = fsgen.keys_device(dist, 64, n, fsgen.seed_for(2, fsgen.DISTS_WIDE.index(dist)), device=gpu)
     ws = fs.Workspace(gpu)
@@ -176,18 +181,14 @@ def test_c2_u64_keys_2e32(gpu, dist):
     torch.cuda.synchronize()
     assert ws.error_word() == 0
     del ws
-    check_non_decreasing(ko)
-    for shift in (0, 48):
-        assert torch.equal(counts16(ki, shift), counts16(ko, shift)), shift
-    # sampled order statistics: #{keys < v} <= i < #{keys <= v}
-    for i in sampled_positions(n, 4, 7):
-        v = int(as_i64(ko[i:i + 1]).item())
-        below = at_most = 0
-        for a in range(0, n, CHUNK):
-            c = as_i64(ki[a:a + CHUNK])
-            below += int((c < v).sum())
-            at_most += int((c <= v).sum())
-        assert below <= i < at_most, i
+    kh = ki.cpu().numpy()
+    del ki
+    compared = 0
+    for off, expected in partitioned_sort(kh, 64, 1 << 28, threads=16):
+        got = ko[off:off + expected.size].cpu().numpy()
+        assert np.array_equal(got, expected), (dist, off, expected.size)
+        compared += expected.size
+    assert compared == n
 
 
 def test_c3_segmented_batch_full(gpu):
