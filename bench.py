@@ -148,7 +148,7 @@ def cpu_baseline(keys_dev, vals_dev, key_bits, val_bytes, budget_s=12.0):
             "sample": f"first 2^26 keys of the workload ({what}), sorted by the C oracle {repsm}x over "
                       f"{threads} threads ({elm:.1f} s) and {reps1}x on one thread ({el1:.1f} s)",
             "single_thread": {"value": one / 1e9, "unit": "Gkeys/s", "cores": 1},
-            "host_cpu": model, "host_cpus_visible": os.cpu_count(),
+            "host_cpu": model, "host_cpus_visible": os.cpu_count(), "host": host_cpu_description(),
             "t_unit_keys_per_s_per_core": {"all_cores": many / threads, "one_core": one}}
 
 
@@ -189,6 +189,117 @@ def build_c3(dev, count=100000, seed=None):
             pools[(b, dname)] = (g, out, sel, offs)
     batch = fs.SegmentBatch.from_array(desc, int(L.sum()), int(L.max()), device=dev, keep=keep)
     return batch, desc, pools, L
+
+
+def segment_active_digits(pool, lengths, key_bits):
+    """Per segment of `pool` (consecutive segments of the given lengths):
+    how many 8-bit digits are not shared by all of its keys (the digits its
+    sort runs passes for).  Plain PyTorch reductions over each digit's
+    values (exact in float32: they are below 256)."""
+    import numpy as np
+    import torch
+    lens = torch.from_numpy(np.asarray(lengths, dtype=np.int64)).to(pool.device)
+    kk = pool.view({16: torch.int16, 32: torch.int32, 64: torch.int64}[key_bits])
+    active = torch.zeros(lens.numel(), dtype=torch.int32, device=pool.device)
+    for j in range(key_bits // 8):
+        d = ((kk >> (8 * j)) & 0xFF).to(torch.float32)
+        hi = torch.segment_reduce(d, "max", lengths=lens)
+        lo = torch.segment_reduce(d, "min", lengths=lens)
+        active += (hi != lo).to(torch.int32)
+        del d, hi, lo
+    return active.cpu().numpy()
+
+
+def c3_algorithmic_bytes(desc, L, pools, tuning):
+    """Algorithmic bytes of one C3 step, per bin, from the bins the
+    classifier picks under `tuning` (segments of at most 64 keys: wave bin;
+    16-bit keys from expand16_min_keys: the 16-bit-digit bin; what fits the
+    LDS bin's bound and 32 KiB; the rest, one workgroup or the large bin):
+      wave and LDS bins   read and write each key once: 2k
+      16-bit-digit bin    histogram read 2 + expansion write 2
+      one-WG / large bin  digit histograms k + 2k per active digit (a
+                          segment with no active digit is copied: 2k)."""
+    import numpy as np
+    kb = desc["key_bits"].astype(np.int64) // 8
+    n = L.astype(np.int64)
+    smax = np.array(list(tuning.small_max_keys), dtype=np.int64)
+    small_max = np.where(kb == 2, smax[0], np.where(kb == 4, smax[1], smax[2]))
+    small_cap = (32768 - 16) // kb
+    wave = n <= 64
+    expand = ~wave & (kb == 2) & (n >= int(tuning.expand16_min_keys))
+    small = ~wave & ~expand & (n <= np.minimum(small_cap, small_max))
+    rest = ~(wave | expand | small)
+    active = np.zeros(n.size, dtype=np.int64)
+    for (b, dname), (g, out, sel, offs) in pools.items():
+        active[sel] = segment_active_digits(g, L[sel], b)
+    rest_bytes = np.where(active > 0, kb * n + 2 * kb * n * active, kb * n + 2 * kb * n)
+    wg = rest & (n <= int(tuning.large_wg_max_keys))
+    out = {"wave": int((2 * kb * n)[wave].sum()), "lds": int((2 * kb * n)[small].sum()),
+           "digit16": int((4 * n)[expand].sum()), "one_workgroup": int(rest_bytes[wg].sum()),
+           "large": int(rest_bytes[rest & ~wg].sum())}
+    keys = {"wave": int(n[wave].sum()), "lds": int(n[small].sum()), "digit16": int(n[expand].sum()),
+            "one_workgroup": int(n[wg].sum()), "large": int(n[rest & ~wg].sum())}
+    return out, keys
+
+
+def oracle_sample_rate(items, budget_s=12.0, threads=None, seed=0, one_at_a_time=False):
+    """The oracle timed on a bounded sample: `items` is a list of (n, fetch)
+    where fetch() returns the host keys of one independent sort (a segment
+    or a job).  Items are drawn with probability proportional to n (so the
+    rate is weighted like the whole batch's keys) and sorted until about
+    budget_s of sorting time: one per thread by oracle.sort, or with
+    one_at_a_time each by oracle.sort_mt over all the threads.  Only the
+    sorts are timed.  Returns (keys/s, sampled keys, sorts, sorting
+    seconds, threads)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    oracle.load()
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    threads = threads or max(1, min(len(os.sched_getaffinity(0)), share, 64))
+    rng = np.random.default_rng(seed)
+    w = np.array([float(it[0]) for it in items])
+    order = rng.choice(len(items), size=min(len(items), 4096), replace=False, p=w / w.sum())
+    done_keys = sorts = 0
+    wall = 0.0
+    step = 1 if one_at_a_time else threads
+    with ThreadPoolExecutor(threads) as ex:
+        pos = 0
+        while pos < len(order) and wall < budget_s:
+            batch = [items[i][1]() for i in order[pos:pos + step]]
+            pos += step
+            t0 = time.perf_counter()
+            if one_at_a_time:
+                oracle.sort_mt(batch[0], threads=threads)
+            else:
+                list(ex.map(oracle.sort, batch))
+            wall += time.perf_counter() - t0
+            done_keys += sum(int(b.size) for b in batch)
+            sorts += len(batch)
+    return done_keys / wall, done_keys, sorts, wall, threads
+
+
+def host_cpu_description():
+    """lscpu's model, sockets, cores per socket and threads (or /proc/cpuinfo's model)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    model = info.get("Model name")
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+        except OSError:
+            model = None
+    return {"model": model or "unknown", "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"), "threads": info.get("CPU(s)"),
+            "process_cpu_share": len(os.sched_getaffinity(0))}
 
 
 def run_c3(args):
@@ -249,6 +360,28 @@ def run_c3(args):
                    "parallelism": "single GPU", "graph": True},
     }
     out["autotune"] = tune_info
+    tuning_used = tuned if tuned is not None else fs.get_tuning()
+    by_bin, keys_by_bin = c3_algorithmic_bytes(desc, L, pools, tuning_used)
+    alg = sum(by_bin.values())
+    achieved = alg / (ms_batched / 1e3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                       "scope": "whole step (every segmented kernel of the graph): algorithmic bytes of "
+                                "the bins the classifier picks, over the step time",
+                       "bytes_per_step_by_bin": by_bin, "keys_by_bin": keys_by_bin}
+    if not args.no_cpu_baseline:
+        items = []
+        for (b, dname), (g, outp, sel, offs) in pools.items():
+            for i, o in zip(sel.tolist(), offs.tolist()):
+                m = int(L[i])
+                items.append((m, (lambda g=g, o=int(o), m=m: g[o:o + m].cpu().numpy())))
+        rate, sk, sorts, wall, thr = oracle_sample_rate(items)
+        out["cpu_baseline"] = {"value": round(rate / 1e9, 4), "unit": "Gkeys/s", "cores": thr, "kind": "oracle",
+                               "sample": f"{sorts} segments ({sk} keys) drawn with probability proportional "
+                                         f"to length, each sorted alone by the C oracle, {thr} at a time "
+                                         f"({wall:.1f} s of sorting); the whole batch at this rate: "
+                                         f"{n / rate:.1f} s",
+                               "host_cpu": host_cpu_description()}
     if args.no_loop_baseline:
         print(json.dumps(out), flush=True)
         return
@@ -280,58 +413,118 @@ def run_c3(args):
     print(json.dumps(out), flush=True)
 
 
+def c4_pools(dev, seed, pool_keys=1 << 28):
+    """Resident inputs of the served stream: one device array of 2^28 keys
+    per (width, distribution) a job can draw; a job's input is a slice of
+    its pool, so every input is in HBM before the trace starts."""
+    import fsgen
+    pools = {}
+    for bits in (16, 32, 64):
+        for di, dist in enumerate(fsgen.valid_dists(bits)):
+            if dist in ("presorted", "reverse"):
+                continue
+            pools[(bits, dist)] = fsgen.keys_device(dist, bits, pool_keys, seed + 64 * bits + di, device=dev)
+    return pools
+
+
+def attach_pool_inputs(jobs, pools):
+    for j in jobs:
+        g = pools[(j.key_bits, j.dist)]
+        off = ((j.seed * 0x9E3779B97F4A7C15) >> 11) % (g.numel() - j.n + 1)
+        j.keys_in = g[off:off + j.n]
+
+
 def run_c4(args):
     """Served stream: Poisson arrivals of sort jobs (sizes log-uniform
     2^10..2^28 keys, widths 16/32/64, mixed distributions), 200 GB device
     budget, continuous batching over 4 streams, against FIFO one job at a
     time.  A seeded prefix of `args.jobs` jobs of the 20k-job stream is
-    served; the arrival rate is 90% of the capacity measured on the first
-    jobs of the same stream."""
+    served.  Every input is resident in HBM before any timing (slices of
+    per-distribution pools).  Capacity = the prefix's keys over its
+    makespan when every job arrives at once; the arrival rate is then rho
+    times the continuous-batching capacity, rho = 0.5 and 0.9, and both
+    servers are run on each trace."""
     import numpy as np
     import torch
     import fsgen
-    from paper_2605_10390_amd.serve import SortServer, make_trace, percentile
+    from paper_2605_10390_amd.serve import SortServer, make_trace, served_stats
     dev = torch.device("cuda:0")
     seed = fsgen.seed_for(4, 0)
     budget = 200 << 30
-    srv = SortServer(dev, budget_bytes=budget, slots=4)
-    srv.serve(make_trace(48, seed + 1, lam=1e9))  # warm-up: module loads, allocator pools
-    calib = make_trace(160, seed + 2, lam=1e9)      # all at t=0: the server saturated
-    t0 = time.perf_counter()
-    srv.serve(calib)
-    cap = sum(j.n for j in calib) / (time.perf_counter() - t0)
-    mean_n = (2.0 ** 28 - 2.0 ** 10) / (18 * np.log(2.0))
-    rho = 0.9
-    lam = rho * cap / mean_n
-    print(f"[bench] c4 capacity {cap / 1e9:.2f} Gkeys/s -> lambda {lam:.1f} jobs/s", file=sys.stderr,
-          flush=True)
-    results = {}
-    for name, kw in (("continuous_batching", dict(slots=4)),
-                     ("fifo_one_at_a_time", dict(slots=1, small_keys=0))):
+    pools = c4_pools(dev, seed + 7)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    modes = (("continuous_batching", dict(slots=4)), ("fifo_one_at_a_time", dict(slots=1, small_keys=0)))
+
+    def serve(lam, kw):
         trace = make_trace(args.jobs, seed, lam=lam)
-        s = SortServer(dev, budget_bytes=budget, **kw)
+        attach_pool_inputs(trace, pools)
+        srv = SortServer(dev, budget_bytes=budget, **kw)
         t0 = time.perf_counter()
-        done = s.serve(trace)
+        done = srv.serve(trace)
         wall = time.perf_counter() - t0
-        ok = [j for j in done if j.done is not None]
-        lat = [j.latency * 1e3 for j in ok]
-        span = max(j.done for j in ok) - min(j.arrival for j in ok)
-        results[name] = {"p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
-                         "gkeys_s": round(sum(j.n for j in ok) / span / 1e9, 3), "jobs": len(ok),
-                         "rejected": sum(1 for j in done if j.rejected), "launches": s.launches,
-                         "peak_device_gb": round(s.peak_used / 2 ** 30, 2), "max_in_flight": s.max_in_flight,
-                         "wall_s": round(wall, 2)}
-        print(f"[bench] c4 {name}: {results[name]}", file=sys.stderr, flush=True)
-    cb = results["continuous_batching"]
-    out = {"metric": METRIC, "value": cb["gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1, "steps": 1,
-           "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "u16/u32/u64 mixed", "data": "synthetic",
-           "config": {"workload": f"served sort stream: seeded prefix of {args.jobs} of 20000 jobs, "
-                                  "Poisson arrivals at 90% of measured capacity, n log-uniform 2^10..2^28, "
-                                  "widths 16/32/64, mixed distributions, 200 GB budget",
-                      "lambda_jobs_s": round(lam, 2), "capacity_gkeys_s": round(cap / 1e9, 3),
+        st = served_stats(done)
+        st.update({"launches": srv.launches, "peak_budgeted_gb": round(srv.peak_used / 2 ** 30, 2),
+                   "max_in_flight": srv.max_in_flight, "wall_s": round(wall, 2)})
+        for j in trace:
+            j.keys_in = None
+        del srv
+        return done, st
+
+    warm = make_trace(48, seed + 1, lam=1e9)
+    attach_pool_inputs(warm, pools)
+    SortServer(dev, budget_bytes=budget, slots=4).serve(warm)  # module loads, the arena's allocation
+    mean_n = float(np.mean([j.n for j in make_trace(args.jobs, seed, lam=1.0)]))
+    capacity = {}
+    for name, kw in modes:
+        done, st = serve(1e12, kw)  # every job arrives at t = 0
+        ok = [j for j in done if j.done is not None and not j.failed]
+        capacity[name] = {"gkeys_s": round(sum(j.n for j in ok) / max(j.done for j in ok) / 1e9, 3),
+                          "failed": st["failed"], "wall_s": st["wall_s"]}
+        print(f"[bench] c4 capacity {name}: {capacity[name]}", file=sys.stderr, flush=True)
+    cap = capacity["continuous_batching"]["gkeys_s"] * 1e9
+    served = {}
+    for rho in (0.5, 0.9):
+        lam = rho * cap / mean_n
+        served[f"rho_{rho}"] = {"lambda_jobs_s": round(lam, 3)}
+        for name, kw in modes:
+            _, st = serve(lam, kw)
+            served[f"rho_{rho}"][name] = st
+            print(f"[bench] c4 rho {rho} {name}: {st}", file=sys.stderr, flush=True)
+    reserved = torch.cuda.max_memory_reserved(dev)
+    failed = sum(capacity[m]["failed"] for m in capacity) + sum(
+        served[r][m].get("failed", 0) for r in served for m, _ in modes)
+    if failed:
+        raise SystemExit(f"{failed} served jobs reported a device error")
+    out = {"metric": METRIC, "value": capacity["continuous_batching"]["gkeys_s"], "unit": "Gkeys/s",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u16/u32/u64 mixed", "data": "synthetic",
+           "config": {"workload": f"served sort stream: seeded prefix of {args.jobs} of 20000 jobs, n log-uniform "
+                                  "2^10..2^28, widths 16/32/64, mixed distributions, 200 GB budget, inputs "
+                                  "resident before arrival; value = continuous-batching capacity (every job "
+                                  "arriving at once); Poisson arrivals at rho = 0.5 and 0.9 of it",
+                      "jobs": args.jobs, "mean_keys_per_job": round(mean_n, 1),
                       "parallelism": "single GPU, 4 streams"},
-           "served": results}
+           "capacity": capacity,
+           "batched_speedup": round(capacity["continuous_batching"]["gkeys_s"] /
+                                    capacity["fifo_one_at_a_time"]["gkeys_s"], 3),
+           "served": served,
+           "device_memory": {"max_reserved_gb": round(reserved / 2 ** 30, 2),
+                             "server_arena_gb": round(budget / 2 ** 30, 2),
+                             "resident_input_pools_gb": round(sum(g.numel() * g.element_size()
+                                                                  for g in pools.values()) / 2 ** 30, 2)}}
+    if not args.no_cpu_baseline:
+        jobs = make_trace(args.jobs, seed, lam=1.0)
+        attach_pool_inputs(jobs, pools)
+        items = [(j.n, (lambda j=j: j.keys_in.cpu().numpy())) for j in jobs]
+        rate, sk, sorts, wall, thr = oracle_sample_rate(items, seed=4, one_at_a_time=True)
+        total = sum(j.n for j in jobs)
+        out["cpu_baseline"] = {"value": round(rate / 1e9, 4), "unit": "Gkeys/s", "cores": thr, "kind": "oracle",
+                               "sample": f"{sorts} jobs of the prefix ({sk} keys) drawn with probability "
+                                         f"proportional to size, each sorted alone by the C oracle split over "
+                                         f"{thr} threads ({wall:.1f} s of sorting); the whole prefix at this "
+                                         f"rate: {total / rate:.1f} s",
+                               "host_cpu": host_cpu_description()}
     print(json.dumps(out), flush=True)
 
 
@@ -623,7 +816,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS) + ["c3", "c4", "stream16", "host32", "c8", "wide128"])
-    ap.add_argument("--jobs", type=int, default=1000, help="served-stream prefix length (c4)")
+    ap.add_argument("--jobs", type=int, default=20000, help="served-stream prefix length (c4)")
     ap.add_argument("--dist", default=None,
                     help="c0/c1/c2a/c2b: key distribution (16-bit: uniform gaussian zipf equal presorted "
                          "reverse; wider: uniform small20 hot90); default uniform")

@@ -14,7 +14,18 @@ device memory free up, under a fixed memory budget:
     polling the events, and free the job's memory and slot at once, so the
     next waiting jobs start while others are still running on the device;
   * a job that could never fit the budget is rejected instead of blocking
-    the queue.
+    the queue;
+  * a job's input is already resident in device memory when it arrives
+    (the caller attaches it as job.keys_in); the server allocates only its
+    output and workspace;
+  * the budget is real memory: one device buffer of budget_bytes is
+    reserved when the server starts (Arena), and every launch's outputs and
+    workspace are carved from it at admission and returned at completion,
+    so the server never holds more than its budget whatever the caching
+    allocator would keep;
+  * after each launch the workspace's error word (word 0) is copied to a
+    pinned host word of the slot; a job whose word is not 0 is marked
+    failed (job.failed, job.error) and its output must not be used.
 
 Every job's result is exactly what a stand-alone sort of it gives (the
 segmented path sorts each segment independently and stably).
@@ -38,7 +49,7 @@ class Job:
     `seed`, arriving `arrival` seconds after the trace starts."""
 
     __slots__ = ("id", "key_bits", "n", "dist", "seed", "arrival", "admitted", "done", "batched",
-                 "rejected", "keys_in", "keys_out", "nbytes")
+                 "rejected", "failed", "error", "keys_in", "keys_out", "nbytes")
 
     def __init__(self, jid, key_bits, n, dist, seed, arrival):
         self.id, self.key_bits, self.n, self.dist, self.seed = jid, key_bits, int(n), dist, seed
@@ -46,6 +57,8 @@ class Job:
         self.admitted = self.done = None
         self.batched = False
         self.rejected = False
+        self.failed = False
+        self.error = 0
         self.keys_in = self.keys_out = None
         self.nbytes = 0
 
@@ -96,6 +109,51 @@ class AdmissionPolicy:
         return group
 
 
+class Arena:
+    """First-fit allocator over one device buffer (the server's whole
+    memory budget, reserved once).  Blocks are 256-byte aligned; freed
+    blocks merge with free neighbours."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes, device):
+        self.size = (int(nbytes) // self.ALIGN) * self.ALIGN
+        self.buf = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free = [(0, self.size)]  # (offset, bytes), sorted by offset
+
+    @classmethod
+    def round(cls, nbytes):
+        return max(cls.ALIGN, (int(nbytes) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN)
+
+    def alloc(self, nbytes):
+        """Offset of a free block of nbytes (rounded up), or None."""
+        nbytes = self.round(nbytes)
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= nbytes:
+                if sz == nbytes:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + nbytes, sz - nbytes)
+                return o
+        return None
+
+    def release(self, off, nbytes):
+        nbytes = self.round(nbytes)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, (off, nbytes))
+        if i + 1 < len(self.free) and off + nbytes == self.free[i + 1][0]:
+            self.free[i] = (off, nbytes + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def view(self, off, nbytes, dtype):
+        return self.buf[off:off + nbytes].view(dtype)
+
+
 class SortServer:
     """Serves a trace of Jobs on one GPU with `slots` concurrent streams."""
 
@@ -103,6 +161,9 @@ class SortServer:
                  batch_jobs=64, batch_keys=1 << 24, keep_outputs=False):
         self.device = torch.device(device)
         self.slots = [torch.cuda.Stream(self.device) for _ in range(slots)]  # default priority
+        # one pinned host word per slot receives the error word of its launch
+        self.err_host = torch.zeros(slots, dtype=torch.int32, pin_memory=True)
+        self.arena = Arena(budget_bytes, self.device)
         self.keep_outputs = keep_outputs
         self.policy = AdmissionPolicy(budget_bytes, self._job_bytes, small_keys, batch_jobs,
                                       batch_keys, self._batch_overhead)
@@ -126,23 +187,30 @@ class SortServer:
                                               max(j.n for j in jobs))
 
     # -- device work --------------------------------------------------------
-    def _make_input(self, job):
-        import fsgen
-        job.keys_in = fsgen.keys_device(job.dist, job.key_bits, job.n, job.seed, device=self.device)
-        job.keys_out = torch.empty_like(job.keys_in)
-
-    def _launch(self, jobs, stream):
+    def _launch(self, jobs, stream, slot, base):
+        """Outputs and workspace are carved, in that order, from the arena
+        block at `base` (its size is the group's budgeted bytes)."""
+        off = base
+        for j in jobs:
+            if j.keys_in is None or j.keys_in.numel() != j.n or j.keys_in.dtype != KEY_DTYPES[j.key_bits]:
+                raise ValueError(f"job {j.id}: keys_in must be a resident tensor of {j.n} "
+                                 f"{j.key_bits}-bit keys")
+            nb = j.n * (j.key_bits // 8)
+            j.keys_out = self.arena.view(off, nb, KEY_DTYPES[j.key_bits])
+            off += Arena.round(nb)
+        ws = Workspace(self.device)
         with torch.cuda.stream(stream):
-            for j in jobs:
-                self._make_input(j)
-            ws = Workspace(self.device)
             if len(jobs) == 1 and not jobs[0].batched:
+                ws.buf = self.arena.view(off, Arena.round(sort_keys_workspace_bytes(jobs[0].n, jobs[0].key_bits)),
+                                         torch.uint8)
                 sort_keys(jobs[0].keys_in, out=jobs[0].keys_out, workspace=ws)
             else:
                 for j in jobs:
                     j.batched = True
-                SegmentBatch([(j.keys_in, j.keys_out, None, None) for j in jobs],
-                             device=self.device).run(ws, stream=stream)
+                batch = SegmentBatch([(j.keys_in, j.keys_out, None, None) for j in jobs], device=self.device)
+                ws.buf = self.arena.view(off, Arena.round(batch.workspace_bytes()), torch.uint8)
+                batch.run(ws, stream=stream)
+            self.err_host[slot:slot + 1].copy_(ws.buf[:4].view(torch.int32), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         self.launches += 1
@@ -168,34 +236,42 @@ class SortServer:
                     continue
                 queue.append(j)
             for slot in list(running):
-                ev, group, nbytes, ws = running[slot]
+                ev, group, nbytes, ws, base = running[slot]
                 if ev.query():
                     t = time.perf_counter() - t0
+                    err = int(self.err_host[slot])
                     for j in group:
                         j.done = t
+                        if err:
+                            j.failed, j.error = True, err
                         if on_done is not None:
                             on_done(j)
-                        if not self.keep_outputs:
-                            j.keys_in = j.keys_out = None
+                        # the output's arena block is reused from now on:
+                        # kept outputs are copied out of it (outside the budget)
+                        j.keys_out = j.keys_out.clone() if self.keep_outputs else None
                     self.used -= nbytes
+                    self.arena.release(base, nbytes)
                     del running[slot]
                     free_slots.append(slot)
             while free_slots and queue:
                 group = self.policy.pick(queue, self.policy.budget - self.used)
                 if not group:
                     break
+                nbytes = sum(Arena.round(self._job_bytes(j)) for j in group)
+                if len(group) > 1:
+                    nbytes += Arena.round(self._batch_overhead(group))
+                base = self.arena.alloc(nbytes)
+                if base is None:
+                    break  # free bytes are split into smaller blocks: wait for completions
                 for _ in group:
                     queue.popleft()
-                nbytes = sum(self._job_bytes(j) for j in group)
-                if len(group) > 1:
-                    nbytes += self._batch_overhead(group)
                 t = time.perf_counter() - t0
                 for j in group:
                     j.admitted = t
                     j.nbytes = nbytes
                 slot = free_slots.pop()
-                ev, ws = self._launch(group, self.slots[slot])
-                running[slot] = (ev, group, nbytes, ws)
+                ev, ws = self._launch(group, self.slots[slot], slot, base)
+                running[slot] = (ev, group, nbytes, ws, base)
                 self.used += nbytes
                 self.peak_used = max(self.peak_used, self.used)
                 self.max_in_flight = max(self.max_in_flight, len(running))
@@ -203,6 +279,24 @@ class SortServer:
                 time.sleep(poll_sleep)
         torch.cuda.synchronize(self.device)
         return jobs
+
+
+def served_stats(jobs):
+    """Latency percentiles (ms) and throughput of the jobs that completed
+    without a device error: p50/p99 over all of them and over the first and
+    second half by arrival (a stable queue keeps the two halves alike)."""
+    ok = [j for j in jobs if j.done is not None and not j.failed]
+    if not ok:
+        return {"jobs": 0}
+    lat = [j.latency * 1e3 for j in ok]
+    half = len(ok) // 2
+    span = max(j.done for j in ok) - min(j.arrival for j in ok)
+    return {"p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+            "p99_first_half_ms": round(percentile(lat[:half], 99), 3) if half else None,
+            "p99_second_half_ms": round(percentile(lat[half:], 99), 3),
+            "gkeys_s": round(sum(j.n for j in ok) / span / 1e9, 3) if span > 0 else None,
+            "jobs": len(ok), "failed": sum(1 for j in jobs if j.failed),
+            "rejected": sum(1 for j in jobs if j.rejected)}
 
 
 def make_trace(count, seed, lam, log2_min=10, log2_max=28, widths=(16, 32, 64)):
