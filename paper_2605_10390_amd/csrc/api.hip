@@ -20,6 +20,11 @@ int device_cu_count() {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+static int ceil_log2(uint64_t n) {
+    int b = 0;
+    while (b < 64 && (1ull << b) < n) ++b;
+    return b;
+}
 
 SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus, bool clobber) {
     SortLayout L;
@@ -63,7 +68,14 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus, bo
         L.bsum = take(4ull * kRadix * L.tile_blocks);
         L.ssum = take(4ull * kRadix * L.tile_supers);
         L.sbase = take(8ull * kRadix * L.tile_supers);
-        L.tile_tickets = take(4ull * L.digits * kXcds * kTicketStride);
+        L.tile_tickets = take(4ull * kPlanSlots * kXcds * kTicketStride);
+        // the sparse-trie plan is offered to wide keys from kTrieMinKeys on
+        // (below that its extra launches cost more than passes it can save)
+        L.trie = key_bytes >= 4 && n >= kTrieMinKeys;
+        if (L.trie) {
+            L.trie_list = take(8ull * kTrieLongMax);
+            L.trie_count = take(4);
+        }
         L.sink = take(16);
         L.pairs16 = key_bytes == 2;
         if (L.pairs16) {
@@ -219,7 +231,13 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     a.ord_pos = opos;
     a.ord_neg = oneg;
     zero.p[1] = a.tickets;
-    zero.words[1] = (uint64_t)L.digits * kXcds * kTicketStride;
+    zero.words[1] = (uint64_t)kPlanSlots * kXcds * kTicketStride;
+    if (L.trie) {
+        a.trie_list = reinterpret_cast<uint64_t*>(w + L.trie_list);
+        a.trie_count = reinterpret_cast<uint32_t*>(w + L.trie_count);
+        zero.p[2] = a.trie_count;
+        zero.words[2] = 1;
+    }
     if (L.pairs16) {
         zero.p[2] = reinterpret_cast<uint32_t*>(w + L.wrap);
         zero.words[2] = 2ull * kHist16Words;
@@ -239,7 +257,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s, L.clobber));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
         for (int j = 0; j < 2; ++j) {
-            if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
+            if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s, false));
             FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
             // pass 1, when it runs, is the last pass and writes the output
             FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, j == 1, s));
@@ -249,15 +267,32 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
                                                          (uint32_t)oneg));
         return FS_OK;
     }
-    FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s));
-    FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s, L.clobber));
-    for (int j = 0; j < L.digits; ++j) {
-        if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s));
+    // sparse keys (n far below 2^p): the plan may sort only a window of the
+    // top ceil(log2 n) bits and leave the trailing bits to the fixup
+    const int trie_bits = L.trie ? ceil_log2(n) : 0;
+    FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, 0, L.hist_groups, s, true));
+    FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_plan(part, L.hist_groups, L.digits, n, hist, base, plan, s, L.clobber,
+                                                  trie_bits));
+    auto run_slot = [&](int j) -> fs_status {
+        if (j > 0 || trie_bits) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s, false));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
         FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, false, s));
+        return FS_OK;
+    };
+    for (int j = 0; j < L.digits; ++j)
+        if (run_slot(j) != FS_OK) return FS_ERR_DEVICE;
+    if (trie_bits) {
+        FS_LAUNCH(FS_KERNEL_AUX, n, launch_trie_fixup(a, kb, val_bytes, s));
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_trie_longruns(a, kb, val_bytes, s));
+        for (int j = kPlanCondSlot; j < kPlanCondSlot + L.digits; ++j)
+            if (run_slot(j) != FS_OK) return FS_ERR_DEVICE;
     }
     FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, keys_in, keys_out, kbytes, s));
     if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
+    if (trie_bits) {
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, a.tmp_k, keys_out, kbytes, s, kPlanCopyTmp));
+        if (val_bytes) FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, a.tmp_v, vals_out, vbytes, s, kPlanCopyTmp));
+    }
     return FS_OK;
 }
 

@@ -15,10 +15,28 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr uint32_t kSpinLimit = 1u << 26;
 
 // Plan words written by the planning kernel and read by every pass kernel.
-// pass j: plan[4j] = active, plan[4j+1] = source buffer, plan[4j+2] = dest.
-// plan[kPlanCopy] = 1 when no pass is active and the input must be copied.
+// Pass slot j (0..15): plan[4j] = active, plan[4j+1] = source buffer,
+// plan[4j+2] = destination, plan[4j+3] = the 8-bit digit it sorts on.
+// plan[kPlanCopy] = 1: the result is the input itself (no pass active, or
+// an even number of clobbering passes), copied from keys_in to the output;
+// plan[kPlanCopyTmp] = 1: the result sits in the temporary buffer.
+// Trie plans (sparse keys, n far below 2^p): slots 0..7 sort the window
+// digits, the fixup kernel sorts each run of equal window prefix in buffer
+// plan[kPlanFixBuf] by the trailing bits below plan[kPlanTrieShift], and
+// slots 8..15 hold a full LSD over every active digit that the fixup turns
+// on (with plan[kPlanCondCopyTmp] as its copy word) only if some run is too
+// long for it.  plan[kPlanRecount0] = 1: slot 0 sorts a digit other than 0,
+// so its tile counts are taken again (the first read counts digit 0).
+constexpr int kPlanSlots = 16;
+constexpr int kPlanCondSlot = 8;
 constexpr int kPlanCopy = 64;
-constexpr int kPlanWords = 68;
+constexpr int kPlanCopyTmp = 65;
+constexpr int kPlanTrie = 66;
+constexpr int kPlanTrieShift = 67;
+constexpr int kPlanFixBuf = 68;
+constexpr int kPlanCondCopyTmp = 69;
+constexpr int kPlanRecount0 = 70;
+constexpr int kPlanWords = 72;
 enum BufSel : uint32_t { kBufIn = 0, kBufOut = 1, kBufTmp = 2 };
 
 struct NoVal {};

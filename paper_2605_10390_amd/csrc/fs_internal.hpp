@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fs_sort.h"
+#include "fs_device.hpp"
 #include <stddef.h>
 #include <stdint.h>
 
@@ -26,12 +27,14 @@ struct SortLayout {
     bool expand16 = false;  // 16-bit keys only: compressed histogram + expansion
     bool pairs16 = false;   // 16-bit keys + payload: tiled passes, keys expanded at the end
     bool clobber = false;   // the input arrays are the passes' second buffer
+    bool trie = false;      // 32/64-bit keys: the plan may take the sparse-trie window
     uint32_t hist_groups = 0;  // workgroups of the histogram kernel
     uint32_t hist16_groups = 0;
     uint32_t tile = 0, scatter_groups = 0;
     uint64_t tiles = 0, tile_blocks = 0, tile_supers = 0;
     size_t err = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0, p16 = 0, th = 0, bsum = 0,
-           ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, part16 = 0, tmp_keys = 0, tmp_vals = 0, total = 0;
+           ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, part16 = 0, tmp_keys = 0, tmp_vals = 0, total = 0,
+           trie_list = 0, trie_count = 0;
 };
 
 // clobber: the input arrays are the passes' second buffer (no temporary copy)
@@ -67,13 +70,17 @@ hipError_t launch_reduce8(const uint32_t* part, uint32_t groups, int digits, uin
 // each value unmapped with the key order masks pos, neg (order_unmap)
 hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, uint64_t count,
                            hipStream_t s, uint32_t pos = 0, uint32_t neg = 0);
+// copies bytes from src to dst when plan[word] is set (kPlanCopy: the
+// input is the result; kPlanCopyTmp: the temporary buffer is)
 hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
-                          hipStream_t s);
+                          hipStream_t s, int word = kPlanCopy);
 
 // ---- tiled reduce-then-scan path (tiled.hip) -------------------------------
 constexpr uint64_t kSuperBlock = 256;  // blocks per super-block of the offset scan
 constexpr uint32_t kXcds = 8;          // tile groups of a scatter launch (one per XCD)
 constexpr uint32_t kTicketStride = 32; // words between ticket counters (one 128-byte line each)
+constexpr uint64_t kTrieMinKeys = 1ull << 22;  // sorts offered the sparse-trie plan
+constexpr uint32_t kTrieLongMax = 1u << 20;    // capacity of the list of long trie runs
 
 struct TiledArgs {
     const void* in_k;
@@ -98,14 +105,29 @@ struct TiledArgs {
     uint32_t* err;
     uint64_t ord_pos = 0;   // key order masks (order_map); both 0: unsigned ascending
     uint64_t ord_neg = 0;
+    uint64_t* trie_list = nullptr;   // sparse-trie plan: starts of runs longer than one thread sorts
+    uint32_t* trie_count = nullptr;  // entries appended to trie_list (zero on entry)
 };
 
 ScatterShape tiled_shape(int key_bytes, int val_bytes);
 int tiled_scatter_per_cu(int key_bytes, int val_bytes);
-hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s);
+// tile counts of slot `pass`'s digit; `first`: the first read of the input,
+// which also totals every digit per workgroup for the plan (slot 0 only)
+hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s,
+                            bool first);
 hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s);
 hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
-                            uint64_t* base, uint32_t* plan, hipStream_t s, bool clobber = false);
+                            uint64_t* base, uint32_t* plan, hipStream_t s, bool clobber = false,
+                            int trie_bits = 0);
+// Sparse-trie fixup: sorts every run of keys that share their bits from
+// plan[kPlanTrieShift] up by the trailing bits below (stable, payloads
+// alongside), in place in buffer plan[kPlanFixBuf]; runs longer than one
+// thread sorts are listed for launch_trie_longruns.
+hipError_t launch_trie_fixup(const TiledArgs& a, int key_bytes, int val_bytes, hipStream_t s);
+// Runs the fixup listed as too long for one thread: each is sorted in LDS by
+// one workgroup when it holds at most kTrieLdsRun keys and is out of order;
+// a longer run out of order switches on the fallback slots.
+hipError_t launch_trie_longruns(const TiledArgs& a, int key_bytes, int val_bytes, hipStream_t s);
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
                                bool skip_keys, hipStream_t s);
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,

@@ -493,23 +493,23 @@ hipError_t launch_expand16(const uint64_t* p16, uint16_t* out, uint64_t first, u
 // Copy src -> dst when the plan found every digit trivial (the sorted
 // result is then the input itself).
 template <typename W>
-__global__ void k_copy_if(const uint32_t* plan, const W* __restrict__ src, W* __restrict__ dst,
+__global__ void k_copy_if(const uint32_t* plan, int word, const W* __restrict__ src, W* __restrict__ dst,
                           uint64_t words) {
-    if (!plan[kPlanCopy]) return;
+    if (!plan[word]) return;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
         dst[i] = src[i];
 }
 
 hipError_t launch_copy_if(const uint32_t* plan, const void* src, void* dst, uint64_t bytes,
-                          hipStream_t s) {
+                          hipStream_t s, int word) {
     if (bytes == 0) return hipSuccess;
     const uintptr_t m = reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes;
     auto grid = [](uint64_t words) { uint64_t g = (words + 255) / 256; return (unsigned)(g > 8192 ? 8192 : g); };
-    if ((m & 15) == 0) k_copy_if<uint4><<<grid(bytes / 16), 256, 0, s>>>(plan, (const uint4*)src, (uint4*)dst, bytes / 16);
-    else if ((m & 3) == 0) k_copy_if<uint32_t><<<grid(bytes / 4), 256, 0, s>>>(plan, (const uint32_t*)src, (uint32_t*)dst, bytes / 4);
-    else if ((m & 1) == 0) k_copy_if<uint16_t><<<grid(bytes / 2), 256, 0, s>>>(plan, (const uint16_t*)src, (uint16_t*)dst, bytes / 2);
-    else k_copy_if<uint8_t><<<grid(bytes), 256, 0, s>>>(plan, (const uint8_t*)src, (uint8_t*)dst, bytes);
+    if ((m & 15) == 0) k_copy_if<uint4><<<grid(bytes / 16), 256, 0, s>>>(plan, word, (const uint4*)src, (uint4*)dst, bytes / 16);
+    else if ((m & 3) == 0) k_copy_if<uint32_t><<<grid(bytes / 4), 256, 0, s>>>(plan, word, (const uint32_t*)src, (uint32_t*)dst, bytes / 4);
+    else if ((m & 1) == 0) k_copy_if<uint16_t><<<grid(bytes / 2), 256, 0, s>>>(plan, word, (const uint16_t*)src, (uint16_t*)dst, bytes / 2);
+    else k_copy_if<uint8_t><<<grid(bytes), 256, 0, s>>>(plan, word, (const uint8_t*)src, (uint8_t*)dst, bytes);
     return hipGetLastError();
 }
 

@@ -70,13 +70,16 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
     __shared__ uint32_t s_all[DX][kRadix];
 
     const K* src;
+    int shift = 0;  // the first read counts digit 0's tiles
     if constexpr (FIRST) {
         src = static_cast<const K*>(a.in_k);
     } else {
         if (!a.plan[4 * pass]) return;
+        // slot 0 is counted by the first read unless it sorts another digit
+        if (pass == 0 && !a.plan[kPlanRecount0]) return;
         src = pass_source<K>(a, a.plan[4 * pass + 1]);
+        shift = 8 * (int)a.plan[4 * pass + 3];
     }
-    const int shift = 8 * pass;
     const int tid = threadIdx.x, wave = tid >> 6, copy = wave % kHistCopies;
     for (int i = tid; i < 2 * TPS * kHistCopies * SETW; i += kTileHistThreads) (&s_t[0][0][0][0])[i] = 0;
     for (int i = tid; i < DX * kRadix; i += kTileHistThreads) (&s_all[0][0])[i] = 0;
@@ -436,7 +439,8 @@ constexpr int kPlanThreads = 1024;
 
 __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(const uint32_t* __restrict__ part, uint32_t groups,
                                                             int digits, uint64_t n, uint64_t* hist,
-                                                            uint64_t* base, uint32_t* plan, bool clobber) {
+                                                            uint64_t* base, uint32_t* plan, bool clobber,
+                                                            int trie_bits) {
     constexpr int Q = kPlanThreads / kRadix;
     __shared__ uint64_t s_h[Q][kRadix];
     const int tid = threadIdx.x, b = tid % kRadix, q = tid / kRadix;
@@ -463,12 +467,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(const uint32_t* __re
         }
         __syncthreads();
     }
-    finish_plan(h, digits, n, hist, base, plan, clobber);
+    finish_plan(h, digits, n, hist, base, plan, clobber, trie_bits);
 }
 
 hipError_t launch_tile_plan(const uint32_t* part, uint32_t groups, int digits, uint64_t n, uint64_t* hist,
-                            uint64_t* base, uint32_t* plan, hipStream_t s, bool clobber) {
-    k_tile_plan<<<1, kPlanThreads, 0, s>>>(part, groups, digits, n, hist, base, plan, clobber);
+                            uint64_t* base, uint32_t* plan, hipStream_t s, bool clobber, int trie_bits) {
+    k_tile_plan<<<1, kPlanThreads, 0, s>>>(part, groups, digits, n, hist, base, plan, clobber, trie_bits);
     return hipGetLastError();
 }
 
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
     const uint32_t d = threadIdx.x;
     const uint64_t blocks = (a.tiles + a.block_tiles - 1) / a.block_tiles;
     const uint64_t supers = (blocks + kSuperBlock - 1) / kSuperBlock;
-    uint64_t run = a.base[(uint64_t)pass * 2 * kRadix + d];
+    uint64_t run = a.base[(uint64_t)a.plan[4 * pass + 3] * 2 * kRadix + d];
     constexpr int kBatch = 32;  // loads in flight per round trip
     for (uint64_t sb0 = 0; sb0 < supers; sb0 += kBatch) {
         uint32_t c[kBatch];
@@ -584,7 +588,7 @@ void k_tile_scatter(TiledArgs a, int pass) {
     }
     K* sink_k = reinterpret_cast<K*>(a.sink);
     VS* sink_v = reinterpret_cast<VS*>(a.sink);
-    const int shift = 8 * pass;
+    const int shift = 8 * (int)a.plan[4 * pass + 3];
 
     // contiguous tile group of this workgroup's XCD; its workgroups take the
     // group's tiles in order from a ticket counter, so the tiles in flight
@@ -767,6 +771,248 @@ void k_tile_scatter(TiledArgs a, int pass) {
 }
 
 // ---------------------------------------------------------------------------
+// Sparse-trie fixup (Algorithm 5: the bins of the trie in order, each bin's
+// entries ordered by their trailing bits).  The window passes have left the
+// keys stably sorted by their bits from `shift` up, so every bin is a run of
+// consecutive keys; runs are short when n is far below 2^p.  Each run is
+// sorted by the whole key (its high bits are equal) by the thread at its
+// first position, with a stable insertion sort in place, payloads moving
+// alongside.  A run longer than kTrieRun keys is listed instead (its first
+// position) for k_trie_longruns; a full list switches on the fallback.
+// Runs are disjoint and found from their high bits only, which no sort
+// changes, so threads never race on what they decide.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTrieRun = 64;
+constexpr uint32_t kTrieLdsRun = 4096;
+constexpr int kTrieThreads = 256;
+
+template <typename K>
+__device__ __forceinline__ void trie_fallback(const TiledArgs& a) {
+    // switch on the fallback slots and their copy word (the same words from
+    // every caller)
+    uint32_t* plan = const_cast<uint32_t*>(a.plan);
+    for (int sl = kPlanCondSlot; sl < kPlanSlots; ++sl)
+        if (plan[4 * sl + 1] != plan[4 * sl + 2])
+            __hip_atomic_store(&plan[4 * sl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&plan[kPlanCopyTmp], plan[kPlanCondCopyTmp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename K, typename V, bool ORD>
+__global__ __launch_bounds__(kTrieThreads) void k_trie_fixup(TiledArgs a) {
+    constexpr bool kHasVals = !std::is_same<V, NoVal>::value;
+    using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
+    if (!a.plan[kPlanTrie]) return;
+    const uint32_t buf = a.plan[kPlanFixBuf];
+    K* keys = static_cast<K*>(buf == kBufOut ? a.out_k : a.tmp_k);
+    VS* vals = nullptr;
+    if constexpr (kHasVals) vals = static_cast<VS*>(buf == kBufOut ? a.out_v : a.tmp_v);
+    const int shift = (int)a.plan[kPlanTrieShift];
+    const K pos = (K)a.ord_pos, neg = (K)a.ord_neg;
+    // keys compare (and runs are found) in the mapped order
+    auto mk = [&](uint64_t i) -> K { return ORD ? order_map<K>(keys[i], pos, neg) : keys[i]; };
+    auto high = [&](K m) -> uint64_t { return (uint64_t)m >> shift; };
+    const uint64_t n = a.n;
+    bool overflow = false;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const K ki = mk(i);
+        const uint64_t h = high(ki);
+        if (i > 0 && high(mk(i - 1)) == h) continue;  // not the first key of its run
+        // the run's extent (up to kTrieRun keys) and whether it is in order
+        uint64_t j = i + 1;
+        bool ordered = true, longrun = false;
+        K prev = ki;
+        while (j < n) {
+            const K kj = mk(j);
+            if (high(kj) != h) break;
+            if (j - i >= kTrieRun) {
+                longrun = true;
+                break;
+            }
+            ordered &= !(kj < prev);
+            prev = kj;
+            ++j;
+        }
+        if (longrun) {
+            const uint32_t slot = atomicAdd(a.trie_count, 1u);
+            if (slot < kTrieLongMax) a.trie_list[slot] = i;
+            else overflow = true;
+            continue;
+        }
+        if (ordered) continue;
+        // stable insertion sort of [i, j): strictly greater keys move up
+        for (uint64_t p = i + 1; p < j; ++p) {
+            const K x = keys[p];
+            const K xm = ORD ? order_map<K>(x, pos, neg) : x;
+            VS v{};
+            if constexpr (kHasVals) v = vals[p];
+            uint64_t q = p;
+            while (q > i) {
+                const K y = keys[q - 1];
+                if (!((ORD ? order_map<K>(y, pos, neg) : y) > xm)) break;
+                keys[q] = y;
+                if constexpr (kHasVals) vals[q] = vals[q - 1];
+                --q;
+            }
+            keys[q] = x;
+            if constexpr (kHasVals) vals[q] = v;
+        }
+    }
+    if (overflow) trie_fallback<K>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Long trie runs: one workgroup per listed run finds the run's end and
+// whether it is in order, 256 keys at a time.  A run out of order of at most
+// kTrieLdsRun keys is loaded into LDS and sorted there by a bitonic network
+// over (mapped key, position in the run) -- positions are distinct, so the
+// order is total and equal keys keep theirs (stable) -- then written back
+// with its payloads.  A longer run out of order switches on the fallback.
+// ---------------------------------------------------------------------------
+template <typename K, typename V, bool ORD>
+__global__ __launch_bounds__(kTrieThreads) void k_trie_longruns(TiledArgs a) {
+    constexpr bool kHasVals = !std::is_same<V, NoVal>::value;
+    using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
+    __shared__ K s_key[kTrieLdsRun];
+    __shared__ VS s_val[kHasVals ? kTrieLdsRun : 1];
+    __shared__ uint16_t s_idx[kTrieLdsRun];
+    __shared__ uint64_t s_end;
+    __shared__ int s_unordered;
+    if (!a.plan[kPlanTrie]) return;
+    const uint32_t listed = *a.trie_count;
+    const uint32_t runs = listed < kTrieLongMax ? listed : kTrieLongMax;
+    if (blockIdx.x >= runs) return;
+    const uint32_t buf = a.plan[kPlanFixBuf];
+    K* keys = static_cast<K*>(buf == kBufOut ? a.out_k : a.tmp_k);
+    VS* vals = nullptr;
+    if constexpr (kHasVals) vals = static_cast<VS*>(buf == kBufOut ? a.out_v : a.tmp_v);
+    const int shift = (int)a.plan[kPlanTrieShift];
+    const K pos = (K)a.ord_pos, neg = (K)a.ord_neg;
+    auto mk = [&](uint64_t i) -> K { return ORD ? order_map<K>(keys[i], pos, neg) : keys[i]; };
+    const uint64_t n = a.n;
+    const int tid = threadIdx.x;
+    for (uint32_t r = blockIdx.x; r < runs; r += gridDim.x) {
+        const uint64_t b = a.trie_list[r];
+        const uint64_t h = (uint64_t)mk(b) >> shift;
+        if (tid == 0) {
+            s_end = n;
+            s_unordered = 0;
+        }
+        __syncthreads();
+        // extent and order, 256 positions per step: the run ends at the
+        // first position past it (or n); a step that holds it is the last
+        for (uint64_t c = b;; c += kTrieThreads) {
+            const uint64_t p = c + tid;
+            bool stop = p >= n;
+            if (!stop) {
+                const K kp = mk(p);
+                stop = ((uint64_t)kp >> shift) != h;
+                if (!stop && p > b && kp < mk(p - 1)) s_unordered = 1;
+            }
+            if (stop) atomicMin(reinterpret_cast<unsigned long long*>(&s_end), (unsigned long long)p);
+            __syncthreads();
+            const uint64_t end_now = s_end;
+            __syncthreads();  // every thread has read it before the next step may lower it
+            if (end_now < c + kTrieThreads) break;
+        }
+        const uint64_t e = s_end;
+        const int unordered = s_unordered;
+        __syncthreads();
+        if (!unordered) continue;
+        const uint64_t len = e - b;
+        if (len > kTrieLdsRun) {
+            if (tid == 0) trie_fallback<K>(a);
+            continue;
+        }
+        // load (mapped keys), bitonic sort of positions, write back
+        uint32_t np2 = 1;
+        while (np2 < len) np2 <<= 1;
+        for (uint32_t i = tid; i < np2; i += kTrieThreads) {
+            if (i < len) {
+                s_key[i] = mk(b + i);
+                if constexpr (kHasVals) s_val[i] = vals[b + i];
+            }
+            s_idx[i] = (uint16_t)i;
+        }
+        __syncthreads();
+        auto before = [&](uint32_t x, uint32_t y) {
+            // a strict total order: the run's keys by (key, position), then
+            // the padding past the run by position
+            const bool xp = x >= len, yp = y >= len;
+            if (xp || yp) return xp && yp ? x < y : yp;
+            return s_key[x] < s_key[y] || (s_key[x] == s_key[y] && x < y);
+        };
+        for (uint32_t k = 2; k <= np2; k <<= 1) {
+            for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                for (uint32_t i = tid; i < np2; i += kTrieThreads) {
+                    const uint32_t l = i ^ jj;
+                    if (l > i) {
+                        const uint32_t x = s_idx[i], y = s_idx[l];
+                        const bool asc = (i & k) == 0;
+                        if (asc ? before(y, x) : before(x, y)) {
+                            s_idx[i] = (uint16_t)y;
+                            s_idx[l] = (uint16_t)x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = tid; i < len; i += kTrieThreads) {
+            const uint32_t x = s_idx[i];
+            keys[b + i] = ORD ? order_unmap<K>(s_key[x], pos, neg) : s_key[x];
+            if constexpr (kHasVals) vals[b + i] = s_val[x];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename K, typename V>
+static void launch_fixup_kv(const TiledArgs& a, hipStream_t s) {
+    const uint64_t want = (a.n + kTrieThreads - 1) / kTrieThreads;
+    const uint32_t grid = (uint32_t)(want < 8192 ? (want ? want : 1) : 8192);
+    if (a.ord_pos | a.ord_neg) k_trie_fixup<K, V, true><<<grid, kTrieThreads, 0, s>>>(a);
+    else k_trie_fixup<K, V, false><<<grid, kTrieThreads, 0, s>>>(a);
+}
+
+template <typename K, typename V>
+static void launch_longruns_kv(const TiledArgs& a, hipStream_t s) {
+    const uint32_t grid = 512;
+    if (a.ord_pos | a.ord_neg) k_trie_longruns<K, V, true><<<grid, kTrieThreads, 0, s>>>(a);
+    else k_trie_longruns<K, V, false><<<grid, kTrieThreads, 0, s>>>(a);
+}
+
+hipError_t launch_trie_longruns(const TiledArgs& a, int key_bytes, int val_bytes, hipStream_t s) {
+    if (key_bytes == 4) {
+        if (val_bytes == 0) launch_longruns_kv<uint32_t, NoVal>(a, s);
+        else if (val_bytes == 4) launch_longruns_kv<uint32_t, uint32_t>(a, s);
+        else launch_longruns_kv<uint32_t, uint64_t>(a, s);
+    } else if (key_bytes == 8) {
+        if (val_bytes == 0) launch_longruns_kv<uint64_t, NoVal>(a, s);
+        else if (val_bytes == 4) launch_longruns_kv<uint64_t, uint32_t>(a, s);
+        else launch_longruns_kv<uint64_t, uint64_t>(a, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trie_fixup(const TiledArgs& a, int key_bytes, int val_bytes, hipStream_t s) {
+    if (key_bytes == 4) {
+        if (val_bytes == 0) launch_fixup_kv<uint32_t, NoVal>(a, s);
+        else if (val_bytes == 4) launch_fixup_kv<uint32_t, uint32_t>(a, s);
+        else launch_fixup_kv<uint32_t, uint64_t>(a, s);
+    } else if (key_bytes == 8) {
+        if (val_bytes == 0) launch_fixup_kv<uint64_t, NoVal>(a, s);
+        else if (val_bytes == 4) launch_fixup_kv<uint64_t, uint32_t>(a, s);
+        else launch_fixup_kv<uint64_t, uint64_t>(a, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Tile shapes and launchers
 // ---------------------------------------------------------------------------
 #define FS_TILED_SHAPES(X)                 \
@@ -808,26 +1054,27 @@ int tiled_scatter_per_cu(int key_bytes, int val_bytes) {
 }
 
 template <typename K, int TILE, bool ORD>
-static void launch_hist_o(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
-    if (pass == 0) k_tile_hist<K, true, TILE, ORD><<<groups, kTileHistThreads, 0, s>>>(a, pass);
+static void launch_hist_o(const TiledArgs& a, int pass, bool first, uint32_t groups, hipStream_t s) {
+    if (first) k_tile_hist<K, true, TILE, ORD><<<groups, kTileHistThreads, 0, s>>>(a, pass);
     else k_tile_hist<K, false, TILE, ORD><<<groups, kTileHistThreads, 0, s>>>(a, pass);
 }
 
 template <typename K, int TILE>
-static void launch_hist_t(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
-    if (a.ord_pos | a.ord_neg) launch_hist_o<K, TILE, true>(a, pass, groups, s);
-    else launch_hist_o<K, TILE, false>(a, pass, groups, s);
+static void launch_hist_t(const TiledArgs& a, int pass, bool first, uint32_t groups, hipStream_t s) {
+    if (a.ord_pos | a.ord_neg) launch_hist_o<K, TILE, true>(a, pass, first, groups, s);
+    else launch_hist_o<K, TILE, false>(a, pass, first, groups, s);
 }
 
-hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s) {
-    if (key_bytes == 1 && a.tile == 4096) launch_hist_t<uint8_t, 4096>(a, pass, groups, s);
-    else if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, groups, s);
-    else if (key_bytes == 2 && a.tile == 8192) launch_hist_t<uint16_t, 8192>(a, pass, groups, s);
-    else if (key_bytes == 2 && a.tile == 16384) launch_hist_t<uint16_t, 16384>(a, pass, groups, s);
-    else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, groups, s);
-    else if (key_bytes == 4 && a.tile == 2048) launch_hist_t<uint32_t, 2048>(a, pass, groups, s);
-    else if (key_bytes == 8 && a.tile == 4096) launch_hist_t<uint64_t, 4096>(a, pass, groups, s);
-    else if (key_bytes == 8 && a.tile == 2048) launch_hist_t<uint64_t, 2048>(a, pass, groups, s);
+hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s,
+                            bool first) {
+    if (key_bytes == 1 && a.tile == 4096) launch_hist_t<uint8_t, 4096>(a, pass, first, groups, s);
+    else if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, first, groups, s);
+    else if (key_bytes == 2 && a.tile == 8192) launch_hist_t<uint16_t, 8192>(a, pass, first, groups, s);
+    else if (key_bytes == 2 && a.tile == 16384) launch_hist_t<uint16_t, 16384>(a, pass, first, groups, s);
+    else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, first, groups, s);
+    else if (key_bytes == 4 && a.tile == 2048) launch_hist_t<uint32_t, 2048>(a, pass, first, groups, s);
+    else if (key_bytes == 8 && a.tile == 4096) launch_hist_t<uint64_t, 4096>(a, pass, first, groups, s);
+    else if (key_bytes == 8 && a.tile == 2048) launch_hist_t<uint64_t, 2048>(a, pass, first, groups, s);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
