@@ -71,6 +71,18 @@ def active_digits(keys, key_bits):
     return out
 
 
+PLAN_BYTE, PLAN_WORDS, PLAN_TRIE = 256, 72, 66  # the plan follows the workspace's error-word block
+
+
+def plan_passes(ws):
+    """The pass slots the device's plan ran (slot j sorted digit
+    plan[4j+3]) and whether it took the sparse-trie window (plus fixup)."""
+    import torch
+    p = ws.buf[PLAN_BYTE:PLAN_BYTE + PLAN_WORDS * 4].view(torch.int32).cpu().tolist()
+    slots = [j for j in range(16) if p[4 * j]]
+    return slots, bool(p[PLAN_TRIE])
+
+
 def scatter_pass_bytes(key_bits, val_bytes, active):
     """Algorithmic bytes per key of every scatter pass that runs.  A 16-bit
     pair sort's second pass writes only the payloads (its keys are expanded
@@ -930,9 +942,19 @@ def main():
     ms_step = ms_total / args.steps
     gkeys = n * args.steps / (ms_total / 1e3) / 1e9
     active = active_digits(keys, key_bits)
-    pass_bytes = scatter_pass_bytes(key_bits, val_bytes, active) if not (key_bits == 16 and val_bytes == 0) else []
+    trie = False
+    if key_bits == 16:
+        pass_bytes = scatter_pass_bytes(key_bits, val_bytes, active) if val_bytes else []
+        bpk = algorithmic_bytes_per_key(key_bits, val_bytes, active)
+    else:
+        # the passes the device's plan ran: one per active digit, or the
+        # sparse-trie window passes followed by the fixup's read of every key
+        # (and payload)
+        slots, trie = plan_passes(ws)
+        pass_bytes = [scatter_bytes_per_key(key_bits, val_bytes)] * len(slots)
+        bpk = (key_bits // 8 + sum(pass_bytes) + (key_bits // 8 + val_bytes if trie else 0) if slots
+               else algorithmic_bytes_per_key(key_bits, val_bytes, [False] * (key_bits // 8)))
     passes = len(pass_bytes)
-    bpk = algorithmic_bytes_per_key(key_bits, val_bytes, active)
     scatter_avg = sum(pass_bytes) / passes if passes else 0
     for name, kinfo in kernels.items():
         if kinfo["launches"]:
@@ -975,7 +997,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
                      "traffic": traffic, "bytes_per_key": dom_bytes_per_key,
                      "keys_per_launch": dom["keys"] // max(dom["launches"], 1),
-                     "active_digits": [int(a) for a in active]},
+                     "active_digits": [int(a) for a in active], "passes_run": passes,
+                     "sparse_trie": trie},
         "hbm_frac_whole_sort": round(n * bpk / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes_per_key": bpk,
         "kernels": {k: {kk2: (round(vv, 4) if isinstance(vv, float) else vv) for kk2, vv in v.items()}

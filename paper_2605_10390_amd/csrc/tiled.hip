@@ -776,14 +776,21 @@ void k_tile_scatter(TiledArgs a, int pass) {
 // keys stably sorted by their bits from `shift` up, so every bin is a run of
 // consecutive keys; runs are short when n is far below 2^p.  Each run is
 // sorted by the whole key (its high bits are equal) by the thread at its
-// first position, with a stable insertion sort in place, payloads moving
-// alongside.  A run longer than kTrieRun keys is listed instead (its first
+// first position, with a stable insertion sort, payloads moving alongside.
+// A workgroup loads a tile of kTrieTile keys (and payloads) with the key
+// before it and kTrieRun keys after it into LDS, finds the runs that start
+// in the tile there and sorts the ones out of order in LDS.  If it sorted
+// any, it writes back the slots it owns -- from its first run start to the
+// end of the run holding its last position -- in one coalesced pass.  A run
+// longer than kTrieRun keys is listed instead (its first
 // position) for k_trie_longruns; a full list switches on the fallback.
 // Runs are disjoint and found from their high bits only, which no sort
-// changes, so threads never race on what they decide.
+// changes, and each position is written only by the workgroup whose tile
+// holds the first position of its run, so nothing races.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTrieRun = 64;
 constexpr uint32_t kTrieLdsRun = 4096;
+constexpr uint32_t kTrieTile = 2048;
 constexpr int kTrieThreads = 256;
 
 template <typename K>
@@ -801,6 +808,11 @@ template <typename K, typename V, bool ORD>
 __global__ __launch_bounds__(kTrieThreads) void k_trie_fixup(TiledArgs a) {
     constexpr bool kHasVals = !std::is_same<V, NoVal>::value;
     using VS = typename std::conditional<kHasVals, V, uint32_t>::type;
+    // a tile of kTrieTile positions, the key before it and kTrieRun keys
+    // after it (a run that starts in the tile ends within them or is long)
+    constexpr uint32_t kSpan = kTrieTile + kTrieRun + 1;
+    __shared__ K s_key[kSpan];
+    __shared__ VS s_val[kHasVals ? kSpan : 1];
     if (!a.plan[kPlanTrie]) return;
     const uint32_t buf = a.plan[kPlanFixBuf];
     K* keys = static_cast<K*>(buf == kBufOut ? a.out_k : a.tmp_k);
@@ -808,55 +820,87 @@ __global__ __launch_bounds__(kTrieThreads) void k_trie_fixup(TiledArgs a) {
     if constexpr (kHasVals) vals = static_cast<VS*>(buf == kBufOut ? a.out_v : a.tmp_v);
     const int shift = (int)a.plan[kPlanTrieShift];
     const K pos = (K)a.ord_pos, neg = (K)a.ord_neg;
-    // keys compare (and runs are found) in the mapped order
-    auto mk = [&](uint64_t i) -> K { return ORD ? order_map<K>(keys[i], pos, neg) : keys[i]; };
     auto high = [&](K m) -> uint64_t { return (uint64_t)m >> shift; };
     const uint64_t n = a.n;
+    const uint64_t tiles = (n + kTrieTile - 1) / kTrieTile;
+    const int tid = threadIdx.x;
     bool overflow = false;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const K ki = mk(i);
-        const uint64_t h = high(ki);
-        if (i > 0 && high(mk(i - 1)) == h) continue;  // not the first key of its run
-        // the run's extent (up to kTrieRun keys) and whether it is in order
-        uint64_t j = i + 1;
-        bool ordered = true, longrun = false;
-        K prev = ki;
-        while (j < n) {
-            const K kj = mk(j);
-            if (high(kj) != h) break;
-            if (j - i >= kTrieRun) {
-                longrun = true;
-                break;
+    // the span of tile t: positions [lo, hi) into slots [off, off + hi - lo)
+    // (slot q holds position t0 - 1 + q); its keys and payloads are loaded
+    // into registers one tile ahead, every load issued at a clamped index
+    constexpr int kLoads = (kSpan + kTrieThreads - 1) / kTrieThreads;
+    K rk[kLoads];
+    VS rv[kLoads];
+    auto span = [&](uint64_t t, uint64_t* lo, uint64_t* hi, uint32_t* off) {
+        const uint64_t t0 = t * kTrieTile;
+        *lo = t0 ? t0 - 1 : 0;
+        *hi = t0 + kTrieTile + kTrieRun < n ? t0 + kTrieTile + kTrieRun : n;
+        *off = t0 ? 0u : 1u;  // tile 0 has no key before it
+    };
+    auto fetch = [&](uint64_t t) {
+        uint64_t lo, hi;
+        uint32_t off;
+        span(t, &lo, &hi, &off);
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) {
+            const uint64_t p = lo + tid + (uint64_t)k * kTrieThreads;
+            const uint64_t pc = p < hi ? p : hi - 1;
+            rk[k] = keys[pc];
+            if constexpr (kHasVals) rv[k] = vals[pc];
+        }
+    };
+    if ((uint64_t)blockIdx.x < tiles) fetch(blockIdx.x);
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t t0 = t * kTrieTile;
+        uint64_t lo, hi;
+        uint32_t off;
+        span(t, &lo, &hi, &off);
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) {
+            const uint64_t p = lo + tid + (uint64_t)k * kTrieThreads;
+            if (p < hi) {
+                s_key[p - lo + off] = ORD ? order_map<K>(rk[k], pos, neg) : rk[k];
+                if constexpr (kHasVals) s_val[p - lo + off] = rv[k];
             }
-            ordered &= !(kj < prev);
-            prev = kj;
-            ++j;
         }
-        if (longrun) {
-            const uint32_t slot = atomicAdd(a.trie_count, 1u);
-            if (slot < kTrieLongMax) a.trie_list[slot] = i;
-            else overflow = true;
-            continue;
-        }
-        if (ordered) continue;
-        // stable insertion sort of [i, j): strictly greater keys move up
-        for (uint64_t p = i + 1; p < j; ++p) {
-            const K x = keys[p];
-            const K xm = ORD ? order_map<K>(x, pos, neg) : x;
-            VS v{};
-            if constexpr (kHasVals) v = vals[p];
-            uint64_t q = p;
-            while (q > i) {
-                const K y = keys[q - 1];
-                if (!((ORD ? order_map<K>(y, pos, neg) : y) > xm)) break;
-                keys[q] = y;
-                if constexpr (kHasVals) vals[q] = vals[q - 1];
-                --q;
+        __syncthreads();
+        if (t + gridDim.x < tiles) fetch(t + gridDim.x);  // in flight while this tile is worked on
+        const uint32_t have = (uint32_t)(hi - lo) + off;  // slots filled: [off, have)
+        // every loaded slot from the tile's first position on: the slots of
+        // runs that start in the tile (slots 1..kTrieTile), including their
+        // ends past it, are this tile's to place
+        for (uint32_t q = 1 + tid; q < have; q += kTrieThreads) {
+            const K kq = s_key[q];
+            const uint64_t h = high(kq);
+            uint32_t b = q;  // the run's first slot (or kTrieRun back)
+            while (b > off && q - b < kTrieRun && high(s_key[b - 1]) == h) --b;
+            if (b == 0 || b > kTrieTile) continue;  // a run of the tile before or after
+            if (q - b >= kTrieRun) continue;        // inside a long run
+            uint32_t e = q + 1;
+            while (e < have && e - b <= kTrieRun && high(s_key[e]) == h) ++e;
+            if (e - b > kTrieRun) {
+                // a long run: listed by its first key, placed by k_trie_longruns
+                if (q == b) {
+                    const uint32_t slot = atomicAdd(a.trie_count, 1u);
+                    if (slot < kTrieLongMax) a.trie_list[slot] = t0 + b - 1;
+                    else overflow = true;
+                }
+                continue;
             }
-            keys[q] = x;
-            if constexpr (kHasVals) vals[q] = v;
+            // rank in the run: keys that sort before this one (smaller, or
+            // equal and earlier: stable)
+            uint32_t rank = 0;
+            for (uint32_t r = b; r < e; ++r) {
+                const K kr = s_key[r];
+                rank += (kr < kq || (kr == kq && r < q)) ? 1u : 0u;
+            }
+            const uint32_t dst = b + rank;
+            if (dst != q) {
+                keys[t0 + dst - 1] = ORD ? order_unmap<K>(kq, pos, neg) : kq;
+                if constexpr (kHasVals) vals[t0 + dst - 1] = s_val[q];
+            }
         }
+        __syncthreads();
     }
     if (overflow) trie_fallback<K>(a);
 }
@@ -969,8 +1013,8 @@ __global__ __launch_bounds__(kTrieThreads) void k_trie_longruns(TiledArgs a) {
 
 template <typename K, typename V>
 static void launch_fixup_kv(const TiledArgs& a, hipStream_t s) {
-    const uint64_t want = (a.n + kTrieThreads - 1) / kTrieThreads;
-    const uint32_t grid = (uint32_t)(want < 8192 ? (want ? want : 1) : 8192);
+    const uint64_t tiles = (a.n + kTrieTile - 1) / kTrieTile;
+    const uint32_t grid = (uint32_t)(tiles < 4096 ? (tiles ? tiles : 1) : 4096);
     if (a.ord_pos | a.ord_neg) k_trie_fixup<K, V, true><<<grid, kTrieThreads, 0, s>>>(a);
     else k_trie_fixup<K, V, false><<<grid, kTrieThreads, 0, s>>>(a);
 }
