@@ -376,12 +376,16 @@ fs_status fs_sort16_host(const void *h_keys_in, void *h_keys_out, uint64_t n, ui
  *     3. consecutive bins are grouped into ranges of at most device_keys
  *        keys, in key order; for each range one more read gathers its keys
  *        on the device, fs_sort_keys sorts them, and they are copied to
- *        their place in h_keys_out.
- *   The input is read (number of ranges + 2) times.  h_keys_in/h_keys_out:
- *   host, n keys, not overlapping (the input is read until the last range);
- *   pinned memory (hipHostMalloc) makes the copies asynchronous.  When every
- *   key is equal the input is copied.  FS_ERR_UNSUPPORTED when one bin of
- *   the histogram holds more than device_keys keys.  The workspace size
+ *        their place in h_keys_out.  A bin holding more than device_keys
+ *        keys is split the same way by its next 16 bits (one more read for
+ *        its histogram, restricted to its keys), down to the lowest bits,
+ *        where such a bin is a single key value and is written out as a run
+ *        of it.
+ *   The input is read (number of ranges + number of histograms + 1) times.
+ *   h_keys_in/h_keys_out: host, n keys, not overlapping (the input is read
+ *   until the last range); pinned memory (hipHostMalloc) makes the copies
+ *   asynchronous.  When every key is equal the input is copied.  The
+ *   workspace size
  *   depends on batch_keys and device_keys.  Blocks until h_keys_out holds
  *   the result.  n == 0 is FS_OK and a no-op.  flags: key order, as for
  *   fs_sort_keys (the spill then works on order-mapped keys).

@@ -231,29 +231,38 @@ __global__ __launch_bounds__(kHostThreads) void k_or_and(const K* __restrict__ k
     }
 }
 
-// compressed 2^16-bin histogram (hist16_add) of bits [shift, shift + 16) of the keys
+// mapped key bits from `s` up (0 when s reaches the key's width)
+__device__ __forceinline__ uint64_t bits_from(uint64_t m, int s) { return s >= 64 ? 0ull : m >> s; }
+
+// compressed 2^16-bin histogram (hist16_add) of the window bits [wshift,
+// wshift + 16) & wmask of the keys whose bits from pshift up equal prefix
 template <typename K>
-__global__ __launch_bounds__(kHostThreads) void k_hist_window(const K* __restrict__ keys, uint64_t n, int shift,
+__global__ __launch_bounds__(kHostThreads) void k_hist_window(const K* __restrict__ keys, uint64_t n, int wshift,
+                                                              uint32_t wmask, int pshift, uint64_t prefix,
                                                               uint32_t* __restrict__ part, uint32_t* wrap_lo,
                                                               uint32_t* wrap_word, uint64_t opos, uint64_t oneg) {
     __shared__ uint32_t cnt[kHist16Words];
     for (int i = threadIdx.x; i < kHist16Words; i += kHostThreads) cnt[i] = 0;
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * kHostThreads;
-    for (uint64_t i = (uint64_t)blockIdx.x * kHostThreads + threadIdx.x; i < n; i += stride)
-        hist16_add(cnt, (uint32_t)(((uint64_t)order_map<K>(keys[i], (K)opos, (K)oneg) >> shift) & 0xFFFFu), 1u,
-                   wrap_lo, wrap_word);
+    for (uint64_t i = (uint64_t)blockIdx.x * kHostThreads + threadIdx.x; i < n; i += stride) {
+        const uint64_t m = (uint64_t)order_map<K>(keys[i], (K)opos, (K)oneg);
+        const bool in = bits_from(m, pshift) == prefix;
+        hist16_add(cnt, in ? (uint32_t)(m >> wshift) & wmask : 0u, in ? 1u : 0u, wrap_lo, wrap_word);
+    }
     __syncthreads();
     uint32_t* dst = part + (uint64_t)blockIdx.x * kHist16Words;
     for (int i = threadIdx.x; i < kHist16Words; i += kHostThreads) dst[i] = cnt[i];
 }
 
-// append the keys whose window value lies in [lo, hi) to out (order within a
-// range does not matter: equal keys are equal bits).  Each block counts the
-// matches of its contiguous chunk, reserves that many slots with one atomic,
-// then writes them (a second read of the chunk, from device memory).
+// append the keys whose bits from pshift up equal prefix and whose window
+// value lies in [lo, hi) to out (order within a range does not matter: equal
+// keys are equal bits).  Each block counts the matches of its contiguous
+// chunk, reserves that many slots with one atomic, then writes them (a
+// second read of the chunk, from device memory).
 template <typename K>
-__global__ __launch_bounds__(kHostThreads) void k_select_range(const K* __restrict__ keys, uint64_t n, int shift,
+__global__ __launch_bounds__(kHostThreads) void k_select_range(const K* __restrict__ keys, uint64_t n, int wshift,
+                                                               uint32_t wmask, int pshift, uint64_t prefix,
                                                                uint32_t lo, uint32_t hi, K* __restrict__ out,
                                                                uint64_t cap, unsigned long long* count,
                                                                uint32_t* err, uint64_t opos, uint64_t oneg) {
@@ -262,8 +271,9 @@ __global__ __launch_bounds__(kHostThreads) void k_select_range(const K* __restri
     const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint64_t c0 = (uint64_t)blockIdx.x * per, c1 = c0 + per < n ? c0 + per : n;
     auto in_range = [&](K k) {
-        const uint32_t v = (uint32_t)(((uint64_t)order_map<K>(k, (K)opos, (K)oneg) >> shift) & 0xFFFFu);
-        return v >= lo && v < hi;
+        const uint64_t m = (uint64_t)order_map<K>(k, (K)opos, (K)oneg);
+        const uint32_t v = (uint32_t)(m >> wshift) & wmask;
+        return bits_from(m, pshift) == prefix && v >= lo && v < hi;
     };
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
@@ -421,63 +431,102 @@ fs_status fs_sort_host(const void* h_keys_in, void* h_keys_out, uint64_t n, int 
         return FS_OK;
     }
     const int top = 63 - __builtin_clzll(diff);
-    const int shift = top >= 15 ? top - 15 : 0;
+    const uint64_t all = key_bits == 64 ? ~0ull : (1ull << key_bits) - 1;
+    // caller's bits of a mapped key value (the inverse of order_map)
+    auto unmap = [&](uint64_t t) {
+        const uint64_t sign = 1ull << (key_bits - 1);
+        return (t ^ ((((t ^ oneg) & sign) != 0) ? oneg : opos)) & all;
+    };
+    auto shr = [](uint64_t x, int s) { return s >= 64 ? 0ull : x >> s; };
 
-    // 2. 2^16-bin histogram of the window [shift, shift + 16)
-    ok = launch_fill_u32(reinterpret_cast<uint32_t*>(hist), 2 * 65536, 0, cs) == hipSuccess;
-    stream_input([&](const char* keys, uint64_t len) {
-        const uint32_t g = std::min<uint32_t>(groups, host_grid(len));
-        if (launch_fill_u32(wrap, 2ull * kHist16Words, 0, cs) != hipSuccess) return false;
-        if (kb == 4)
-            k_hist_window<uint32_t><<<g, kHostThreads, 0, cs>>>((const uint32_t*)keys, len, shift, part, wrap,
-                                                                wrap + kHist16Words, opos, oneg);
-        else
-            k_hist_window<uint64_t><<<g, kHostThreads, 0, cs>>>((const uint64_t*)keys, len, shift, part, wrap,
-                                                                wrap + kHist16Words, opos, oneg);
-        return launch_ok() && launch_merge16(part, g, wrap, wrap + kHist16Words, hist, cs, true) == hipSuccess;
-    });
+    // 2 and 3, for the keys whose mapped bits from pshift up equal prefix:
+    // the 2^16-bin histogram of the 16 bits below pshift, then ranges of
+    // consecutive window values that fit the device, in order, each gathered,
+    // sorted and copied back; a bin holding more keys than the device takes
+    // is split again by its next 16 bits, and at the lowest window such a bin
+    // is one key value, written out as a run of it.  The first call covers
+    // every key: the bits above the top differing bit are the same in all.
     std::vector<uint64_t> h(65536);
-    ok = ok && hipMemcpy(h.data(), hist, kHistBytes, hipMemcpyDeviceToHost) == hipSuccess;
-    if (!ok) return FS_ERR_DEVICE;
-
-    // 3. ranges of consecutive window values that fit the device, in order
     uint64_t placed = 0;
-    for (uint32_t v0 = 0; v0 < 65536;) {
-        uint64_t cnt = 0;
-        uint32_t v1 = v0;
-        while (v1 < 65536 && cnt + h[v1] <= device_keys) cnt += h[v1++];
-        if (v1 == v0) return FS_ERR_UNSUPPORTED;  // one window value holds more keys than the device takes
-        if (cnt) {
-            ok = launch_fill_u32(reinterpret_cast<uint32_t*>(acc + 2), 2, 0u, cs) == hipSuccess;
-            stream_input([&](const char* keys, uint64_t len) {
-                if (kb == 4)
-                    k_select_range<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>(
-                        (const uint32_t*)keys, len, shift, v0, v1, (uint32_t*)range, cnt, acc + 2, serr, opos, oneg);
-                else
-                    k_select_range<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>(
-                        (const uint64_t*)keys, len, shift, v0, v1, (uint64_t*)range, cnt, acc + 2, serr, opos, oneg);
-                return launch_ok();
-            });
-            unsigned long long got = 0;
-            ok = ok && hipMemcpy(&got, acc + 2, sizeof got, hipMemcpyDeviceToHost) == hipSuccess;
-            if (!ok || got != cnt) return FS_ERR_DEVICE;
-            // the previous range's copy back must have left the sorted buffer
-            ok = hipStreamWaitEvent(cs, back.drained, 0) == hipSuccess;
-            size_t ib = inner;
-            if (!ok || fs_sort_keys(range, sorted, cnt, key_bits, flags, ws + o_inner, &ib, cs) != FS_OK)
-                return FS_ERR_DEVICE;
-            uint32_t e = 0;  // the range sort's error word
-            ok = hipEventRecord(back.sorted, cs) == hipSuccess &&
-                 hipStreamWaitEvent(back.s, back.sorted, 0) == hipSuccess &&
-                 hipMemcpyAsync(out + placed * kb, sorted, cnt * kb, hipMemcpyDeviceToHost, back.s) == hipSuccess &&
-                 hipEventRecord(back.drained, back.s) == hipSuccess &&
-                 hipStreamSynchronize(cs) == hipSuccess &&
-                 hipMemcpy(&e, err, sizeof e, hipMemcpyDeviceToHost) == hipSuccess;
-            if (!ok || e != 0) return FS_ERR_DEVICE;
-            placed += cnt;
+    auto visit = [&](auto&& self, uint64_t prefix, int pshift) -> fs_status {
+        const int wshift = pshift > 16 ? pshift - 16 : 0;
+        const uint32_t wmask = (uint32_t)((1ull << (pshift - wshift)) - 1);
+        ok = launch_fill_u32(reinterpret_cast<uint32_t*>(hist), 2 * 65536, 0, cs) == hipSuccess;
+        stream_input([&](const char* keys, uint64_t len) {
+            const uint32_t g = std::min<uint32_t>(groups, host_grid(len));
+            if (launch_fill_u32(wrap, 2ull * kHist16Words, 0, cs) != hipSuccess) return false;
+            if (kb == 4)
+                k_hist_window<uint32_t><<<g, kHostThreads, 0, cs>>>((const uint32_t*)keys, len, wshift, wmask, pshift,
+                                                                    prefix, part, wrap, wrap + kHist16Words, opos, oneg);
+            else
+                k_hist_window<uint64_t><<<g, kHostThreads, 0, cs>>>((const uint64_t*)keys, len, wshift, wmask, pshift,
+                                                                    prefix, part, wrap, wrap + kHist16Words, opos, oneg);
+            return launch_ok() && launch_merge16(part, g, wrap, wrap + kHist16Words, hist, cs, true) == hipSuccess;
+        });
+        ok = ok && hipMemcpy(h.data(), hist, kHistBytes, hipMemcpyDeviceToHost) == hipSuccess;
+        if (!ok) return FS_ERR_DEVICE;
+        std::vector<uint64_t> hv(h.begin(), h.begin() + (size_t)wmask + 1);  // h is reused below this level
+        for (uint32_t v0 = 0; v0 <= wmask;) {
+            if (hv[v0] > device_keys) {
+                const uint64_t sub = (prefix << (pshift - wshift)) | v0;
+                if (wshift == 0) {
+                    // one key value: its run goes straight to the output
+                    ok = hipStreamSynchronize(back.s) == hipSuccess;
+                    if (!ok) return FS_ERR_DEVICE;
+                    const uint64_t value = unmap(sub);
+                    for (uint64_t i = 0; i < hv[v0]; ++i) {
+                        if (kb == 4) reinterpret_cast<uint32_t*>(out)[placed + i] = (uint32_t)value;
+                        else reinterpret_cast<uint64_t*>(out)[placed + i] = value;
+                    }
+                    placed += hv[v0];
+                } else {
+                    const fs_status st = self(self, sub, wshift);
+                    if (st != FS_OK) return st;
+                }
+                ++v0;
+                continue;
+            }
+            uint64_t cnt = 0;
+            uint32_t v1 = v0;
+            while (v1 <= wmask && hv[v1] <= device_keys && cnt + hv[v1] <= device_keys) cnt += hv[v1++];
+            if (cnt) {
+                ok = launch_fill_u32(reinterpret_cast<uint32_t*>(acc + 2), 2, 0u, cs) == hipSuccess;
+                stream_input([&](const char* keys, uint64_t len) {
+                    if (kb == 4)
+                        k_select_range<uint32_t><<<host_grid(len), kHostThreads, 0, cs>>>(
+                            (const uint32_t*)keys, len, wshift, wmask, pshift, prefix, v0, v1, (uint32_t*)range, cnt,
+                            acc + 2, serr, opos, oneg);
+                    else
+                        k_select_range<uint64_t><<<host_grid(len), kHostThreads, 0, cs>>>(
+                            (const uint64_t*)keys, len, wshift, wmask, pshift, prefix, v0, v1, (uint64_t*)range, cnt,
+                            acc + 2, serr, opos, oneg);
+                    return launch_ok();
+                });
+                unsigned long long got = 0;
+                ok = ok && hipMemcpy(&got, acc + 2, sizeof got, hipMemcpyDeviceToHost) == hipSuccess;
+                if (!ok || got != cnt) return FS_ERR_DEVICE;
+                // the previous range's copy back must have left the sorted buffer
+                ok = hipStreamWaitEvent(cs, back.drained, 0) == hipSuccess;
+                size_t ib = inner;
+                if (!ok || fs_sort_keys(range, sorted, cnt, key_bits, flags, ws + o_inner, &ib, cs) != FS_OK)
+                    return FS_ERR_DEVICE;
+                uint32_t e = 0;  // the range sort's error word
+                ok = hipEventRecord(back.sorted, cs) == hipSuccess &&
+                     hipStreamWaitEvent(back.s, back.sorted, 0) == hipSuccess &&
+                     hipMemcpyAsync(out + placed * kb, sorted, cnt * kb, hipMemcpyDeviceToHost, back.s) == hipSuccess &&
+                     hipEventRecord(back.drained, back.s) == hipSuccess &&
+                     hipStreamSynchronize(cs) == hipSuccess &&
+                     hipMemcpy(&e, err, sizeof e, hipMemcpyDeviceToHost) == hipSuccess;
+                if (!ok || e != 0) return FS_ERR_DEVICE;
+                placed += cnt;
+            }
+            v0 = v1;
         }
-        v0 = v1;
-    }
+        return FS_OK;
+    };
+    const int pshift0 = top + 1;  // bits from here up are common to every key
+    const fs_status st = visit(visit, shr(oa_h[0], pshift0), pshift0);
+    if (st != FS_OK) return st;
     uint32_t e = 0;
     ok = hipStreamSynchronize(back.s) == hipSuccess &&
          hipMemcpy(&e, serr, sizeof e, hipMemcpyDeviceToHost) == hipSuccess;

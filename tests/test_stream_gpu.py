@@ -173,11 +173,41 @@ def test_host_sort_wide_edges(gpu):
             assert np.array_equal(out.numpy(), np.sort(k)), (bits, n)
         eq = np.full(100_000, 0xDEADBEEF, dtype=dt)  # every key equal: a copy
         assert np.array_equal(fs.sort_host(torch.from_numpy(eq), device_keys=16, device=gpu).numpy(), eq)
-    # one histogram bin with more keys than a device range holds
+
+
+def test_host_sort_splits_oversized_bins(gpu):
+    """Window bins holding more keys than one device range are split again
+    by their next 16 bits, down to single key values (written out as runs)."""
+    rng = np.random.default_rng(8)
+    # skewed 32-bit keys: hot values share window bins past the range size
     k = fsgen.keys_host("hot90", 32, 200_000, 3)
-    with pytest.raises(fs.FsError) as e:
-        fs.sort_host(torch.from_numpy(k), batch_keys=1 << 16, device_keys=1024, device=gpu)
-    assert e.value.status == fs.FS_ERR_UNSUPPORTED
+    out = fs.sort_host(torch.from_numpy(k), batch_keys=1 << 16, device_keys=1024, device=gpu)
+    assert np.array_equal(out.numpy(), oracle.sort(k))
+    # one 64-bit value holds 60% of the keys: every level's bin of it is too
+    # big, down to the lowest 16 bits, where it is one value
+    n = 200_003
+    k = rng.integers(0, 1 << 63, n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, n, dtype=np.uint64)
+    k[rng.random(n) < 0.6] = np.uint64(0x0123456789ABCDEF)
+    out = fs.sort_host(torch.from_numpy(k), batch_keys=1 << 15, device_keys=4096, device=gpu)
+    assert np.array_equal(out.numpy(), oracle.sort(k))
+    # half the keys share their top 32 bits and differ below: split twice,
+    # then ranges that fit
+    k = rng.integers(0, 1 << 63, n, dtype=np.uint64)
+    half = rng.random(n) < 0.5
+    k[half] = (np.uint64(0xCAFEF00D) << np.uint64(32)) | rng.integers(0, 1 << 32, int(half.sum()), dtype=np.uint64)
+    out = fs.sort_host(torch.from_numpy(k), batch_keys=1 << 15, device_keys=4096, device=gpu)
+    assert np.array_equal(out.numpy(), oracle.sort(k))
+
+
+@pytest.mark.parametrize("key_type,desc", [("signed", False), ("unsigned", True)])
+def test_host_sort_split_bins_in_other_orders(gpu, key_type, desc):
+    rng = np.random.default_rng(21)
+    n = 100_001
+    k = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    k[rng.random(n) < 0.5] = np.uint32(0x80000001)  # one value past the range size, sign bit set
+    out = fs.sort_host(torch.from_numpy(k), batch_keys=1 << 14, device_keys=2048, key_type=key_type,
+                       descending=desc, device=gpu)
+    assert np.array_equal(out.numpy(), oracle.sort_ordered(k, key_type=key_type, descending=desc))
 
 
 def test_host_sort_wide_large_matches_threaded_oracle(gpu):
