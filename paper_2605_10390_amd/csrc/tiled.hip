@@ -421,6 +421,13 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
 
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
                               uint32_t* wrap_word, hipStream_t s) {
+    if (a.tile == 8192) {
+        if (a.ord_pos | a.ord_neg)
+            k_tile_hist16<8192, true><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
+        else
+            k_tile_hist16<8192, false><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
+        return hipGetLastError();
+    }
     if (a.tile != 4096) return hipErrorInvalidValue;
     if (a.ord_pos | a.ord_neg)
         k_tile_hist16<4096, true><<<groups, kHist16Threads, 0, s>>>(a, part16, wrap_lo, wrap_word);
@@ -547,8 +554,12 @@ __global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
 // input order and the per-wave ranks (wave_rank) are stable.
 //
 // The loop is software-pipelined: the next tile's keys, payloads, offsets
-// and ticket are requested right after the first barrier and consumed at
-// the top of the next iteration.  Every global load and store in the loop is
+// and ticket are requested in this iteration and consumed at the top of the
+// next one -- right after the first barrier, or with LATE only once this
+// tile is staged, so that neither prefetch occupies registers while the
+// tile is ranked (what lets a 16-item, 8192-key tile fit two workgroups per
+// CU without spilling: longer per-digit runs, fewer partial lines).  The
+// ticket is always taken after the first barrier.  Every global load and store in the loop is
 // issued unconditionally (out-of-range lanes load a valid address and store
 // to the workspace's sink word), so the number of memory operations between
 // a request and its use is fixed and the wait at the top of the loop leaves
@@ -670,8 +681,8 @@ void k_tile_scatter(TiledArgs a, int pass) {
                     reinterpret_cast<u32x4*>(s_keys)[v] = ORD ? order_map_vec<K>(nkv[r], a.ord_pos, a.ord_neg) : nkv[r];
             }
             // payloads of this tile: copied out of the prefetch registers,
-            // or (kLateVals) used from them directly, the next tile's
-            // payloads being requested only after staging
+            // or (kLateVals) used from them directly, the next tile's keys
+            // and payloads being requested only after staging
             VS val[ITEMS];
             if constexpr (kHasVals && !kLateVals) {
 #pragma unroll
@@ -685,8 +696,11 @@ void k_tile_scatter(TiledArgs a, int pass) {
             const uint64_t tn = tlo + s_next;
             const bool more = tn < thi;
             if (tid == 0) ticket = atomicAdd(ctr, 1u);
-            fetch_keys(more ? tn : t);  // the last fetch repeats this tile and is not used
-            if constexpr (!kLateVals) fetch_vals(more ? tn : t);
+            // the last fetch repeats this tile and is not used
+            if constexpr (!kLateVals) {
+                fetch_keys(more ? tn : t);
+                fetch_vals(more ? tn : t);
+            }
 
             // 16-bit keys share a register with their rank (rank < T < 2^16)
             constexpr bool kPack = sizeof(K) == 2;
@@ -742,7 +756,10 @@ void k_tile_scatter(TiledArgs a, int pass) {
                     if constexpr (kHasVals) s_vals[p] = kLateVals ? nval[k] : val[k];
                 }
             }
-            if constexpr (kLateVals) fetch_vals(more ? tn : t);
+            if constexpr (kLateVals) {
+                fetch_keys(more ? tn : t);
+                fetch_vals(more ? tn : t);
+            }
             __syncthreads();
 
 #pragma unroll
@@ -1063,7 +1080,7 @@ hipError_t launch_trie_fixup(const TiledArgs& a, int key_bytes, int val_bytes, h
     X(uint8_t, NoVal, 512, 8, false)       \
     X(uint8_t, uint32_t, 512, 8, false)    \
     X(uint8_t, uint64_t, 512, 8, false)    \
-    X(uint16_t, uint32_t, 512, 8, false)   \
+    X(uint16_t, uint32_t, 512, 16, true)   \
     X(uint16_t, uint64_t, 512, 8, false)   \
     X(uint32_t, NoVal, 512, 8, false)      \
     X(uint32_t, uint32_t, 512, 8, false)   \
