@@ -184,6 +184,41 @@ __device__ __forceinline__ void hist16_add_n(uint32_t* cnt, const uint32_t* key,
     }
 }
 
+// N compressed-histogram adds of one count each (spread keys, every one in
+// range).  An add of one can carry out of a 16-bit half only if that half
+// read 0xFFFF, so one compare per add screens for wraps; the exact tests of
+// hist16_add then run only in a wave where some lane saw a full half.  With
+// a tile row `tc` (128 words of packed 16-bit counts of the low 8 bits) each
+// key is counted there as well: its half there is the same as in `cnt`
+// (bit 0 of the key).  Every add is issued before any result is examined.
+template <int N>
+__device__ __forceinline__ void hist16_add_ones(uint32_t* cnt, const uint32_t* key, uint32_t* tc,
+                                                uint32_t* wrap_lo, uint32_t* wrap_word) {
+    uint32_t old[N], sft[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        sft[e] = (key[e] & 1u) << 4;
+        old[e] = atomicAdd(&cnt[key[e] >> 1], 1u << sft[e]);
+    }
+    if (tc) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) atomicAdd(&tc[(key[e] & 0xFFu) >> 1], 1u << sft[e]);
+    }
+    bool full = false;
+#pragma unroll
+    for (int e = 0; e < N; ++e) full |= ((old[e] >> sft[e]) & 0xFFFFu) == 0xFFFFu;
+    if (__builtin_expect(full, 0)) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            const uint32_t inc = 1u << sft[e];
+            const bool word_wrap = (old[e] + inc) < old[e];
+            const bool lo_wrap = ((old[e] & 0xFFFFu) + (inc & 0xFFFFu)) > 0xFFFFu;
+            if (word_wrap) atomicAdd(&wrap_word[key[e] >> 1], 1u);
+            if (lo_wrap) atomicAdd(&wrap_lo[key[e] >> 1], 1u);
+        }
+    }
+}
+
 // Exclusive scan of one value per thread over the first 256 threads of a
 // block (4 waves); every thread of the block must call it.  `wsum` is LDS
 // scratch of at least 4 words.  Returns the exclusive prefix for threads

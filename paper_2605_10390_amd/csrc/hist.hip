@@ -105,6 +105,15 @@ __global__ __launch_bounds__(kHist16Threads) void k_hist16c(
             uint32_t k[8], c[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) k[e] = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            // no lane past the end and no two equal neighbours in any lane:
+            // an add of one per key
+            bool runs = !in;
+#pragma unroll
+            for (int e = 0; e < 7; ++e) runs |= k[e + 1] == k[e];
+            if (ballot(runs) == 0) {
+                hist16_add_ones<8>(cnt, k, nullptr, wrap_lo, wrap_word);
+                continue;
+            }
             uint32_t run = 1;
 #pragma unroll
             for (int e = 0; e < 7; ++e) {

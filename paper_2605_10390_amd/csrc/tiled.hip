@@ -170,14 +170,28 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
                 const int32_t first = (int32_t)(v * VK) - (int32_t)sh;
                 const bool whole = first >= 0 && first + VK <= (int32_t)cnt &&
                                    (uint32_t)first / TILE == (uint32_t)(first + VK - 1) / TILE;
-                bool same = whole;
-#pragma unroll
-                for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
-                // one add for a whole wave holding one key value inside one tile
                 const uint64_t active = ballot(true);
                 const uint64_t kw =
                     ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)k[0] >> 32)) << 32) |
                     __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)k[0]);
+                if (!skewed && ballot(whole) == active && ballot((uint64_t)k[0] == kw) != active) {
+                    // spread digits, every lane's vector inside the step and
+                    // inside one tile: an add of one per key
+                    uint32_t* tc = &s_t[par][(uint32_t)first / TILE][copy][0];
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const uint32_t d = digit_of<K>(k[e], shift);
+                        atomicAdd(&tc[d >> 1], 1u << ((d & 1u) << 4));
+                    }
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) count_all(k[e], true);
+                    __builtin_amdgcn_sched_barrier(0);
+                    continue;
+                }
+                bool same = whole;
+#pragma unroll
+                for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
+                // one add for a whole wave holding one key value inside one tile
                 const uint32_t set0 = whole ? (uint32_t)first / TILE : 0xFFFFFFFFu;
                 const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
                 if (ballot(same && (uint64_t)k[0] == kw && set0 == setw) == active) {
@@ -346,46 +360,57 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
                 const int32_t first = (int32_t)(v * VK) - (int32_t)sh;
                 const bool whole = first >= 0 && first + VK <= (int32_t)cntk &&
                                    (uint32_t)first / TILE == (uint32_t)(first + VK - 1) / TILE;
-                bool same = whole;
-#pragma unroll
-                for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
                 const uint64_t active = ballot(true);
                 const uint32_t kw = __builtin_amdgcn_readfirstlane((uint32_t)k[0]);
-                const uint32_t set0 = whole ? (uint32_t)first / TILE : 0xFFFFFFFFu;
-                const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
-                if (ballot(same && (uint32_t)k[0] == kw && set0 == setw) == active) {
-                    // a whole wave holding one key value inside one tile: one add each
-                    if (lanes_below(active) == 0) {
-                        const uint32_t c = (uint32_t)VK * popc64(active);
-                        hist16_add(cnt, kw, c, wrap_lo, wrap_word);
-                        const uint32_t d = kw & 0xFFu;
-                        atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
-                    }
+                const uint64_t lead = ballot((uint32_t)k[0] == kw);
+                if (popc64(lead) < kSkewLanes && ballot(whole) == active) {
+                    // spread keys, every lane's vector inside the step and
+                    // inside one tile: an add of one per key, in the
+                    // histogram and in the tile's digit-0 counts
+                    uint32_t kk[VK];
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) kk[e] = k[e];
+                    hist16_add_ones<VK>(cnt, kk, &s_t[par][(uint32_t)first / TILE][copy][0], wrap_lo, wrap_word);
                 } else {
-                    // all adds issued before any carry check (hist16_add_n);
-                    // keys outside the range add 0
-                    // lanes sharing the leader's (tile, key) add once (checked
-                    // on the first element, kept if it paid)
-                    uint32_t kk[VK], cc[VK], st[VK];
-                    bool skewed = false;
+                    bool same = whole;
 #pragma unroll
-                    for (int e = 0; e < VK; ++e) {
-                        const int32_t idx = first + e;
-                        const bool in = idx >= 0 && idx < (int32_t)cntk;
-                        kk[e] = k[e];
-                        st[e] = in ? (uint32_t)idx / TILE : 0u;
-                        cc[e] = in ? 1u : 0u;
-                        if (e == 0 || skewed) {
-                            uint32_t shared;
-                            cc[e] = leader_count((st[e] << 16) | kk[e], in, &shared);
-                            if (e == 0) skewed = shared >= kSkewLanes;
+                    for (int e = 1; e < VK; ++e) same &= k[e] == k[0];
+                    const uint32_t set0 = whole ? (uint32_t)first / TILE : 0xFFFFFFFFu;
+                    const uint32_t setw = __builtin_amdgcn_readfirstlane(set0);
+                    if (ballot(same && (uint32_t)k[0] == kw && set0 == setw) == active) {
+                        // a whole wave holding one key value inside one tile: one add each
+                        if (lanes_below(active) == 0) {
+                            const uint32_t c = (uint32_t)VK * popc64(active);
+                            hist16_add(cnt, kw, c, wrap_lo, wrap_word);
+                            const uint32_t d = kw & 0xFFu;
+                            atomicAdd(&s_t[par][setw][copy][d >> 1], c << ((d & 1) * 16));
                         }
-                    }
-                    hist16_add_n<VK>(cnt, kk, cc, wrap_lo, wrap_word);
+                    } else {
+                        // all adds issued before any carry check (hist16_add_n);
+                        // keys outside the range add 0; lanes sharing the
+                        // leader's (tile, key) add once (checked on the first
+                        // element, kept if it paid)
+                        uint32_t kk[VK], cc[VK], st[VK];
+                        bool skewed = false;
 #pragma unroll
-                    for (int e = 0; e < VK; ++e) {
-                        const uint32_t d = kk[e] & 0xFFu;
-                        if (cc[e]) atomicAdd(&s_t[par][st[e]][copy][d >> 1], cc[e] << ((d & 1) * 16));
+                        for (int e = 0; e < VK; ++e) {
+                            const int32_t idx = first + e;
+                            const bool in = idx >= 0 && idx < (int32_t)cntk;
+                            kk[e] = k[e];
+                            st[e] = in ? (uint32_t)idx / TILE : 0u;
+                            cc[e] = in ? 1u : 0u;
+                            if (e == 0 || skewed) {
+                                uint32_t shared;
+                                cc[e] = leader_count((st[e] << 16) | kk[e], in, &shared);
+                                if (e == 0) skewed = shared >= kSkewLanes;
+                            }
+                        }
+                        hist16_add_n<VK>(cnt, kk, cc, wrap_lo, wrap_word);
+#pragma unroll
+                        for (int e = 0; e < VK; ++e) {
+                            const uint32_t d = kk[e] & 0xFFu;
+                            if (cc[e]) atomicAdd(&s_t[par][st[e]][copy][d >> 1], cc[e] << ((d & 1) * 16));
+                        }
                     }
                 }
             }
