@@ -252,53 +252,84 @@ __device__ __forceinline__ T scan256_exclusive(T x, T* wsum, T* total) {
 // lanes sharing its digit whatever order the ORs took; the lowest of them
 // clears the word and advances cnt[d], the wave's running count of d.
 // Returns (count of d before this item) + (peers below this lane).
+// FULL: every lane is valid (no lane masking at all).  The OR is waited for
+// before the word is read back, and the leader's writes before the next
+// item (a form that issues the reads right behind the OR, with no waits,
+// measured slower on spread keys).
+constexpr uint32_t kLgkmWait0 = 0xC07F;  // s_waitcnt lgkmcnt(0), other counters free
+template <bool FULL = false>
 __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint64_t* peers_w,
                                               uint32_t* cnt_w) {
-    const uint64_t lane_bit = 1ull << (threadIdx.x & 63);
-    if (valid) atomicOr(&peers_w[d], lane_bit);
-    __builtin_amdgcn_wave_barrier();
-    uint64_t peers = 0;
-    uint32_t before = 0;
-    if (valid) {
-        peers = peers_w[d];
-        before = cnt_w[d];
+    if constexpr (FULL) {
+        atomicOr(&peers_w[d], 1ull << (threadIdx.x & 63));
+        __builtin_amdgcn_s_waitcnt(kLgkmWait0);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t peers = peers_w[d];
+        const uint32_t before = cnt_w[d];
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t below = lanes_below(peers);
+        const uint32_t rank = before + below;
+        if (below == 0) {
+            peers_w[d] = 0;
+            cnt_w[d] = before + popc64(peers);
+        }
+        __builtin_amdgcn_s_waitcnt(kLgkmWait0);
+        __builtin_amdgcn_wave_barrier();
+        return rank;
+    } else {
+        const uint64_t lane_bit = 1ull << (threadIdx.x & 63);
+        if (valid) atomicOr(&peers_w[d], lane_bit);
+        __builtin_amdgcn_wave_barrier();
+        uint64_t peers = 0;
+        uint32_t before = 0;
+        if (valid) {
+            peers = peers_w[d];
+            before = cnt_w[d];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t below = lanes_below(peers);
+        if (valid && below == 0) {
+            peers_w[d] = 0;
+            cnt_w[d] = before + popc64(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+        return before + below;
     }
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t below = lanes_below(peers);
-    if (valid && below == 0) {
-        peers_w[d] = 0;
-        cnt_w[d] = before + popc64(peers);
-    }
-    __builtin_amdgcn_wave_barrier();
-    return before + below;
+}
+
+// number of set bits of a lane mask, counted as two 32-bit halves so that
+// comparisons on it stay scalar
+__device__ __forceinline__ uint32_t popc_mask(uint64_t m) {
+    return (uint32_t)__builtin_popcount((uint32_t)m) + (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
 }
 
 // wave_rank with a fast path for the digit of the wave's first valid lane:
-// the lanes holding it are ranked by their position among themselves, so
-// they never touch the LDS word every one of them would OR into (a
-// same-address conflict as wide as the group).  When that digit is every
-// valid lane's (presorted, reverse-sorted, hot-key input) nothing else is
-// done; when it is shared by at least kRankLeaderLanes lanes (skewed keys)
-// the other lanes are ranked by wave_rank, which reads and updates other
-// digits' counts only.
+// when at least kRankLeaderLanes lanes hold it (presorted, reverse-sorted,
+// hot-key or skewed input) they are ranked by their position among
+// themselves, so they never touch the LDS word every one of them would OR
+// into (a same-address conflict as wide as the group), and only the other
+// lanes, if any, are ranked by wave_rank, which reads and updates other
+// digits' counts only.  Valid lanes must be a prefix of the wave (lane 0
+// then holds the first valid digit whenever any lane is valid).
 constexpr uint32_t kRankLeaderLanes = 8;
+template <bool FULL = false>
 __device__ __forceinline__ uint32_t wave_rank_uniform_first(uint32_t d, bool valid, uint64_t* peers_w,
                                                             uint32_t* cnt_w) {
-    const uint64_t vm = ballot(valid);
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xFFFFFFFFu);
-    const uint64_t m = ballot(valid && d == d0);
-    if (vm != 0 && (m == vm || popc64(m) >= kRankLeaderLanes)) {
-        const bool mine = valid && d == d0;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t m = ballot((FULL || valid) && d == d0);
+    if (popc_mask(m) >= kRankLeaderLanes) {
+        const uint64_t vm = FULL ? ~0ull : ballot(valid);
+        const bool mine = (FULL || valid) && d == d0;
         const uint32_t before = cnt_w[d0];
         const uint32_t below = lanes_below(m);
         __builtin_amdgcn_wave_barrier();
         if (mine && below == 0) cnt_w[d0] = before + popc64(m);
         __builtin_amdgcn_wave_barrier();
         if (m == vm) return before + below;
-        const uint32_t r = wave_rank(d, valid && !mine, peers_w, cnt_w);
+        const uint32_t r = wave_rank<false>(d, (FULL || valid) && !mine, peers_w, cnt_w);
         return mine ? before + below : r;
     }
-    return wave_rank(d, valid, peers_w, cnt_w);
+    return wave_rank<FULL>(d, valid, peers_w, cnt_w);
 }
 
 }  // namespace fs

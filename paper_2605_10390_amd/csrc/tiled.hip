@@ -738,14 +738,22 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 if constexpr (kPack) kr[k] = kk;
                 else key[k] = kk;
             }
+            // a full tile (every tile but the last) ranks without lane masks
+            const bool full = count == (uint32_t)T;
+            auto rank_items = [&](auto full_c) {
+                constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-                const bool valid = wbase + k * kWave + lane < count;
-                const K kk = kPack ? (K)kr[k] : key[kPack ? 0 : k];
-                const uint32_t r = wave_rank_uniform_first(digit_of<K>(kk, shift), valid, s_peers[wave], s_wcnt[wave]);
-                if constexpr (kPack) kr[k] |= r << 16;
-                else kr[k] = r;
-            }
+                for (int k = 0; k < ITEMS; ++k) {
+                    const bool valid = FULL || wbase + k * kWave + lane < count;
+                    const K kk = kPack ? (K)kr[k] : key[kPack ? 0 : k];
+                    const uint32_t r =
+                        wave_rank_uniform_first<FULL>(digit_of<K>(kk, shift), valid, s_peers[wave], s_wcnt[wave]);
+                    if constexpr (kPack) kr[k] |= r << 16;
+                    else kr[k] = r;
+                }
+            };
+            if (full) rank_items(std::true_type{});
+            else rank_items(std::false_type{});
             __syncthreads();
 
             // tile histogram from the wave counts, its exclusive scan, and
