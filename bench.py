@@ -85,22 +85,37 @@ def plan_passes(ws):
 
 def scatter_pass_bytes(key_bits, val_bytes, active):
     """Algorithmic bytes per key of every scatter pass that runs.  A 16-bit
-    pair sort's second pass writes only the payloads (its keys are expanded
-    from the 16-bit histogram), so it moves kb bytes per key fewer."""
+    pair sort's first pass writes, of each key, only the high byte the second
+    pass sorts by (nothing when it is the only pass); the second pass reads
+    that byte and writes only the payloads, the sorted keys being expanded
+    from the 16-bit histogram."""
     kb, full = key_bits // 8, scatter_bytes_per_key(key_bits, val_bytes)
-    return [full - (kb if key_bits == 16 and val_bytes and j == 1 else 0)
-            for j, a in enumerate(active) if a]
+    if key_bits == 16 and val_bytes:
+        out = []
+        if active[0]:
+            out.append(kb + val_bytes + (1 if active[1] else 0) + val_bytes)
+        if active[1]:
+            out.append(1 + 2 * val_bytes)
+        return out
+    return [full for a in active if a]
 
 
 def algorithmic_bytes_per_key(key_bits, val_bytes, active):
     """Whole sort: one read of the keys for the histograms, then every pass
     that runs reads and writes key + payload; a 16-bit keys-only sort is one
-    read plus one write of the keys (expansion).  For 16-bit pairs the second
-    pass's key write is replaced by the expansion's: the same bytes.  With no
-    pass to run, the sort is the histogram read plus a copy."""
+    read plus one write of the keys (expansion), 16-bit pairs as in
+    scatter_pass_bytes plus that expansion.  With no pass to run, the sort is
+    the histogram read plus a copy."""
     kb = key_bits // 8
     if key_bits == 16 and val_bytes == 0:
         return 2 * kb
+    if key_bits == 16:
+        # histogram read, the passes, the expansion's key write; the payload
+        # copy when no pass runs; the high-byte copy (read 2, write 1) when
+        # only the second pass runs
+        passes = scatter_pass_bytes(key_bits, val_bytes, active)
+        extra = 2 * val_bytes if not passes else (kb + 1 if active[1] and not active[0] else 0)
+        return kb + sum(passes) + kb + extra
     passes = sum(active)
     if passes == 0:
         return kb + 2 * (kb + val_bytes)

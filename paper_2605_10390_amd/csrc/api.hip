@@ -88,8 +88,9 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus, bo
             L.p16 = take(8ull * 65537);
         }
         // the passes' second buffer: none with clobber (the input serves);
-        // a 16-bit pair sort's keys use the output (the last pass stores no
-        // keys, they are expanded from the histogram afterwards)
+        // none for the keys of a 16-bit pair sort (its first pass writes
+        // only their high bytes, into the output, which the second pass
+        // reads and the expansion from the histogram then overwrites)
         L.clobber = clobber;
         if (!clobber && !L.pairs16) L.tmp_keys = take((size_t)n * key_bytes);
         if (!clobber && val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
@@ -256,12 +257,19 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part16, L.hist16_groups, wrap, wrap + kHist16Words, h16, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s, L.clobber));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
-        for (int j = 0; j < 2; ++j) {
-            if (j > 0) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s, false));
-            FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
-            // pass 1, when it runs, is the last pass and writes the output
-            FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, j == 1, s));
-        }
+        // pass 0 writes the payloads and, into the output key buffer, the
+        // high byte of every mapped key; pass 1 (when it runs, the last)
+        // sorts the payloads by those bytes, read as one-byte keys that
+        // need no further mapping
+        a.narrow = static_cast<uint8_t*>(keys_out);
+        TiledArgs an = a;
+        an.ord_pos = an.ord_neg = 0;
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, 0, s));
+        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, 0, L.scatter_groups, s));
+        FS_LAUNCH(FS_KERNEL_AUX, 0, launch_narrow_copy(a, s));
+        FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(an, 1, 1, L.hist_groups, s, false));
+        FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(an, 1, s));
+        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter_narrow(an, val_bytes, 1, L.scatter_groups, s));
         FS_LAUNCH(FS_KERNEL_AUX, 0, launch_copy_if(plan, vals_in, vals_out, vbytes, s));
         FS_LAUNCH(FS_KERNEL_EXPAND, n, launch_expand16(p16, static_cast<uint16_t*>(keys_out), 0, n, s, (uint32_t)opos,
                                                          (uint32_t)oneg));
@@ -276,7 +284,7 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
     auto run_slot = [&](int j) -> fs_status {
         if (j > 0 || trie_bits) FS_LAUNCH(FS_KERNEL_HISTOGRAM, n, launch_tile_hist(a, kb, j, L.hist_groups, s, false));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, j, s));
-        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, false, s));
+        FS_LAUNCH(FS_KERNEL_SCATTER, n, launch_tile_scatter(a, kb, val_bytes, j, L.scatter_groups, s));
         return FS_OK;
     };
     for (int j = 0; j < L.digits; ++j)

@@ -107,6 +107,12 @@ struct TiledArgs {
     uint64_t ord_neg = 0;
     uint64_t* trie_list = nullptr;   // sparse-trie plan: starts of runs longer than one thread sorts
     uint32_t* trie_count = nullptr;  // entries appended to trie_list (zero on entry)
+    // 16-bit pair sorts: n bytes holding, in the order of the first pass's
+    // output, the high byte of every (mapped) key.  The first pass writes
+    // them instead of the keys; the second pass counts and scatters them as
+    // one-byte keys (its digit), as the sorted keys themselves are rebuilt
+    // from the 2^16-bin histogram.  Null for every other sort.
+    uint8_t* narrow = nullptr;
 };
 
 ScatterShape tiled_shape(int key_bytes, int val_bytes);
@@ -128,8 +134,16 @@ hipError_t launch_trie_fixup(const TiledArgs& a, int key_bytes, int val_bytes, h
 // one workgroup when it holds at most kTrieLdsRun keys and is out of order;
 // a longer run out of order switches on the fallback slots.
 hipError_t launch_trie_longruns(const TiledArgs& a, int key_bytes, int val_bytes, hipStream_t s);
+// 16-bit keys (pair sorts only) write just their high bytes to a.narrow
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
-                               bool skip_keys, hipStream_t s);
+                               hipStream_t s);
+// second pass of a 16-bit pair sort: the bytes in a.narrow are the keys
+// (digit 0), only payloads are written; tiles as for 16-bit keys
+hipError_t launch_tile_scatter_narrow(const TiledArgs& a, int val_bytes, int pass, uint32_t groups,
+                                      hipStream_t s);
+// a.narrow[i] = high byte of the mapped key i of the input, when the plan
+// skips the first pass of a 16-bit pair sort and runs the second
+hipError_t launch_narrow_copy(const TiledArgs& a, hipStream_t s);
 hipError_t launch_tile_hist16(const TiledArgs& a, uint32_t groups, uint32_t* part16, uint32_t* wrap_lo,
                               uint32_t* wrap_word, hipStream_t s);
 

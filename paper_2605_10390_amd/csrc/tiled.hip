@@ -56,7 +56,11 @@ __device__ __forceinline__ const K* pass_source(const TiledArgs& a, uint32_t sel
 // part[g][j][b] receives its totals of digit j == b for the pass plan.
 // ---------------------------------------------------------------------------
 constexpr int kHistCopies = 2;
-constexpr int kHistVecs = 4;  // 16-byte vectors per thread and step (plus one for misalignment)
+// 16-byte vectors per thread and step (plus one for misalignment): two for
+// one-byte keys, whose 16 keys a vector each would otherwise hold too many
+// registers
+template <typename K>
+constexpr int hist_vecs() { return sizeof(K) == 1 ? 2 : 4; }
 
 template <typename K, bool FIRST, int TILE, bool ORD>
 __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int pass) {
@@ -64,6 +68,7 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
     constexpr int VK = 16 / sizeof(K);
     constexpr int DX = FIRST ? D : 1;  // digits counted per workgroup (index 0 unused)
     constexpr int SETW = kRadix / 2;   // words of one packed tile histogram
+    constexpr int kHistVecs = hist_vecs<K>();
     constexpr int TPS = kHistVecs * kTileHistThreads * VK / TILE;  // tiles per step
     static_assert(TPS >= 1 && TPS * TILE == kHistVecs * kTileHistThreads * VK, "whole tiles per step");
     __shared__ uint32_t s_t[2][TPS][kHistCopies][SETW];
@@ -79,6 +84,10 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         if (pass == 0 && !a.plan[kPlanRecount0]) return;
         src = pass_source<K>(a, a.plan[4 * pass + 1]);
         shift = 8 * (int)a.plan[4 * pass + 3];
+        if (sizeof(K) == 1 && a.narrow) {  // second pass of a 16-bit pair sort
+            src = reinterpret_cast<const K*>(a.narrow);
+            shift = 0;
+        }
     }
     const int tid = threadIdx.x, wave = tid >> 6, copy = wave % kHistCopies;
     for (int i = tid; i < 2 * TPS * kHistCopies * SETW; i += kTileHistThreads) (&s_t[0][0][0][0])[i] = 0;
@@ -125,6 +134,7 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         // skew_all answers it for digit j of the first pass's totals.
         bool skewed = false;
         uint32_t skew_all = 0;
+        uint32_t hot = 0;  // the step's leading digit (when skewed)
         {
             const uint32_t v = tid;
             const bool in0 = v < nv && (int32_t)(v * VK) - (int32_t)sh >= 0;
@@ -133,6 +143,7 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
             const uint32_t d0 = digit_of<K>(k0[0], shift);
             const uint32_t lead = __builtin_amdgcn_readfirstlane(in0 ? d0 : 0xFFFFFFFFu);
             skewed = popc64(ballot(in0 && d0 == lead)) >= kSkewLanes;
+            hot = lead;
             if constexpr (FIRST) {
 #pragma unroll
                 for (int j = 1; j < D; ++j) {
@@ -204,6 +215,26 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
                             for (int j = 1; j < D; ++j) atomicAdd(&s_all[j][digit_of<uint64_t>(kw, 8 * j)], c);
                         }
                     }
+                } else if (VK >= 8 && skewed && active == ~0ull && ballot(whole && set0 == setw) == active) {
+                    // skewed digits of keys of up to 16 bits, the whole wave
+                    // inside one tile: each lane counts its keys holding the
+                    // step's leading digit and the wave sums those counts
+                    // (across all 64 lanes) into one add; other keys add one
+                    // each.  (Wider keys, 4 or 2 per vector, do not repay
+                    // the wave sum and take the leader path.)
+                    uint32_t* tc = &s_t[par][setw][copy][0];
+                    uint32_t nh = 0;
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const uint32_t d = digit_of<K>(k[e], shift);
+                        if (d == hot) ++nh;
+                        else atomicAdd(&tc[d >> 1], 1u << ((d & 1u) << 4));
+                    }
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) count_all(k[e], true);
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) nh += __shfl_xor(nh, o, 64);
+                    if (lanes_below(active) == 0 && nh) atomicAdd(&tc[hot >> 1], nh << ((hot & 1u) << 4));
                 } else if (skewed) {
                     // lanes sharing the leader's (tile, digit) add once
 #pragma unroll
@@ -590,7 +621,13 @@ __global__ __launch_bounds__(kRadix) void k_super_base(TiledArgs a, int pass) {
 // a request and its use is fixed and the wait at the top of the loop leaves
 // the previous tile's stores in flight.
 // ---------------------------------------------------------------------------
-template <typename K, typename V, int THREADS, int ITEMS, bool LATE, bool SKIPK, bool ORD>
+// What a pass writes of its keys: the keys (kOutKeys), nothing (kOutNone:
+// the second pass of a 16-bit pair sort, whose sorted keys are expanded
+// from the 2^16-bin histogram), or only their high bytes, to a.narrow
+// (kOutHigh: the first pass of a 16-bit pair sort, for the second pass).
+constexpr int kOutKeys = 0, kOutNone = 1, kOutHigh = 2;
+
+template <typename K, typename V, int THREADS, int ITEMS, bool LATE, int KOUT, bool ORD>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_tile_scatter(TiledArgs a, int pass) {
     constexpr int W = THREADS / kWave;
@@ -614,7 +651,10 @@ void k_tile_scatter(TiledArgs a, int pass) {
 
     if (!a.plan[4 * pass]) return;
     const uint32_t src_sel = a.plan[4 * pass + 1], dst_sel = a.plan[4 * pass + 2];
-    const K* src_k = pass_source<K>(a, src_sel);
+    // the second pass of a 16-bit pair sort reads the high key bytes as
+    // one-byte keys
+    const bool narrow_src = sizeof(K) == 1 && a.narrow != nullptr;
+    const K* src_k = narrow_src ? reinterpret_cast<const K*>(a.narrow) : pass_source<K>(a, src_sel);
     K* dst_k = static_cast<K*>(dst_sel == kBufOut ? a.out_k : a.tmp_k);
     const VS* src_v = nullptr;
     VS* dst_v = nullptr;
@@ -624,7 +664,10 @@ void k_tile_scatter(TiledArgs a, int pass) {
     }
     K* sink_k = reinterpret_cast<K*>(a.sink);
     VS* sink_v = reinterpret_cast<VS*>(a.sink);
-    const int shift = 8 * (int)a.plan[4 * pass + 3];
+    const int shift = narrow_src ? 0 : 8 * (int)a.plan[4 * pass + 3];
+    // the high bytes matter only if the second pass runs
+    const bool write_high = KOUT == kOutHigh && a.plan[4 * 1] != 0;
+    uint8_t* sink_b = reinterpret_cast<uint8_t*>(a.sink);
 
     // contiguous tile group of this workgroup's XCD; its workgroups take the
     // group's tiles in order from a ticket counter, so the tiles in flight
@@ -727,8 +770,8 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 fetch_vals(more ? tn : t);
             }
 
-            // 16-bit keys share a register with their rank (rank < T < 2^16)
-            constexpr bool kPack = sizeof(K) == 2;
+            // keys of up to 16 bits share a register with their rank (rank < T < 2^16)
+            constexpr bool kPack = sizeof(K) <= 2;
             K key[kPack ? 1 : ITEMS];
             uint32_t kr[ITEMS];  // kPack: key | rank << 16; otherwise the rank
 #pragma unroll
@@ -804,9 +847,11 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 const uint64_t dst = s_dst[digit_of<K>(kk, shift)] + qq;
                 const bool ok = in && dst < a.n;
                 bad_dst |= in && !(dst < a.n);
-                // SKIPK: the keys of this pass's output are written elsewhere
-                // (expanded from the 2^16-bin histogram)
-                if constexpr (!SKIPK) *(ok ? dst_k + dst : sink_k) = ORD ? order_unmap<K>(kk, (K)a.ord_pos, (K)a.ord_neg) : kk;
+                if constexpr (KOUT == kOutKeys)
+                    *(ok ? dst_k + dst : sink_k) = ORD ? order_unmap<K>(kk, (K)a.ord_pos, (K)a.ord_neg) : kk;
+                if constexpr (KOUT == kOutHigh) {  // the mapped key's high byte
+                    if (write_high) *(ok ? a.narrow + dst : sink_b) = (uint8_t)((uint32_t)kk >> 8);
+                }
                 if constexpr (kHasVals) *(ok ? dst_v + dst : sink_v) = s_vals[qq];
                 // keep the compiler from hoisting every slot's loads at once
                 if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -1141,7 +1186,7 @@ int tiled_scatter_per_cu(int key_bytes, int val_bytes) {
     hipError_t e = hipErrorInvalidValue;
 #define FS_OCC(K, V, THR, IT, LATE)                                                                  \
     if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>())                                   \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE, false, false>, THR, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_scatter<K, V, THR, IT, LATE, kOutKeys, false>, THR, 0);
     FS_TILED_SHAPES(FS_OCC)
 #undef FS_OCC
     return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
@@ -1162,6 +1207,7 @@ static void launch_hist_t(const TiledArgs& a, int pass, bool first, uint32_t gro
 hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_t groups, hipStream_t s,
                             bool first) {
     if (key_bytes == 1 && a.tile == 4096) launch_hist_t<uint8_t, 4096>(a, pass, first, groups, s);
+    else if (key_bytes == 1 && a.tile == 8192) launch_hist_t<uint8_t, 8192>(a, pass, first, groups, s);
     else if (key_bytes == 2 && a.tile == 4096) launch_hist_t<uint16_t, 4096>(a, pass, first, groups, s);
     else if (key_bytes == 2 && a.tile == 8192) launch_hist_t<uint16_t, 8192>(a, pass, first, groups, s);
     else if (key_bytes == 2 && a.tile == 16384) launch_hist_t<uint16_t, 16384>(a, pass, first, groups, s);
@@ -1181,23 +1227,67 @@ hipError_t launch_tile_offsets(const TiledArgs& a, int pass, hipStream_t s) {
     return hipGetLastError();
 }
 
+// 16-bit keys are tiled only in pair sorts, whose first pass writes the
+// high key bytes (kOutHigh); every other width writes its keys
+template <typename K, typename V, int THR, int IT, bool LATE>
+static hipError_t scatter_launch(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
+    constexpr int kout = (sizeof(K) == 2 && !std::is_same<V, NoVal>::value) ? kOutHigh : kOutKeys;
+    if (a.ord_pos | a.ord_neg) k_tile_scatter<K, V, THR, IT, LATE, kout, true><<<groups, THR, 0, s>>>(a, pass);
+    else k_tile_scatter<K, V, THR, IT, LATE, kout, false><<<groups, THR, 0, s>>>(a, pass);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_scatter(const TiledArgs& a, int key_bytes, int val_bytes, int pass, uint32_t groups,
-                               bool skip_keys, hipStream_t s) {
-#define FS_LAUNCH_SHAPE(K, V, THR, IT, LATE)                                              \
-    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>()) {                      \
-        const bool ord = (a.ord_pos | a.ord_neg) != 0;                                    \
-        if (skip_keys && sizeof(K) == 2 && val_size<V>() != 0) {                          \
-            if (ord) k_tile_scatter<K, V, THR, IT, LATE, true, true><<<groups, THR, 0, s>>>(a, pass); \
-            else k_tile_scatter<K, V, THR, IT, LATE, true, false><<<groups, THR, 0, s>>>(a, pass);    \
-        } else {                                                                          \
-            if (ord) k_tile_scatter<K, V, THR, IT, LATE, false, true><<<groups, THR, 0, s>>>(a, pass); \
-            else k_tile_scatter<K, V, THR, IT, LATE, false, false><<<groups, THR, 0, s>>>(a, pass);    \
-        }                                                                                 \
-        return hipGetLastError();                                                         \
-    }
+                               hipStream_t s) {
+#define FS_LAUNCH_SHAPE(K, V, THR, IT, LATE)                                         \
+    if (key_bytes == (int)sizeof(K) && val_bytes == val_size<V>())                   \
+        return scatter_launch<K, V, THR, IT, LATE>(a, pass, groups, s);
     FS_TILED_SHAPES(FS_LAUNCH_SHAPE)
 #undef FS_LAUNCH_SHAPE
     return hipErrorInvalidValue;
+}
+
+// the second pass of a 16-bit pair sort: one-byte keys (already mapped)
+// on the 16-bit pair shape's tiles
+template <typename K, typename V, int THR, int IT, bool LATE>
+static hipError_t scatter_narrow_launch(const TiledArgs& a, int pass, uint32_t groups, hipStream_t s) {
+    if constexpr (sizeof(K) == 2 && !std::is_same<V, NoVal>::value) {
+        k_tile_scatter<uint8_t, V, THR, IT, LATE, kOutNone, false><<<groups, THR, 0, s>>>(a, pass);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_scatter_narrow(const TiledArgs& a, int val_bytes, int pass, uint32_t groups,
+                                      hipStream_t s) {
+    if (!a.narrow) return hipErrorInvalidValue;
+#define FS_LAUNCH_NARROW(K, V, THR, IT, LATE)                                        \
+    if (sizeof(K) == 2 && val_bytes == val_size<V>() && val_bytes != 0)              \
+        return scatter_narrow_launch<K, V, THR, IT, LATE>(a, pass, groups, s);
+    FS_TILED_SHAPES(FS_LAUNCH_NARROW)
+#undef FS_LAUNCH_NARROW
+    return hipErrorInvalidValue;
+}
+
+// High bytes of the (mapped) input keys of a 16-bit pair sort whose first
+// pass is skipped (every key has the same low byte) while the second runs.
+__global__ void k_narrow_copy(TiledArgs a) {
+    if (a.plan[0] || !a.plan[4]) return;
+    const uint16_t* in = static_cast<const uint16_t*>(a.in_k);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        uint16_t k = in[i];
+        if (a.ord_pos | a.ord_neg) k = order_map<uint16_t>(k, (uint16_t)a.ord_pos, (uint16_t)a.ord_neg);
+        a.narrow[i] = (uint8_t)(k >> 8);
+    }
+}
+
+hipError_t launch_narrow_copy(const TiledArgs& a, hipStream_t s) {
+    if (!a.narrow || a.n == 0) return hipErrorInvalidValue;
+    uint64_t g = (a.n + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_narrow_copy<<<(unsigned)g, 256, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 }  // namespace fs

@@ -25,17 +25,22 @@ def test_active_digits():
 
 
 def test_pass_bytes():
-    # 16-bit pairs: the second pass stores only payloads
-    assert bench.scatter_pass_bytes(16, 4, [True, True]) == [12, 10]
-    assert bench.scatter_pass_bytes(16, 4, [False, True]) == [10]
-    assert bench.scatter_pass_bytes(16, 4, [True, False]) == [12]
+    # 16-bit pairs: the first pass stores the high key byte (none when it
+    # is the only pass), the second reads that byte and stores only payloads
+    assert bench.scatter_pass_bytes(16, 4, [True, True]) == [2 + 4 + 1 + 4, 1 + 4 + 4]
+    assert bench.scatter_pass_bytes(16, 4, [False, True]) == [1 + 4 + 4]
+    assert bench.scatter_pass_bytes(16, 4, [True, False]) == [2 + 4 + 4]
     assert bench.scatter_pass_bytes(32, 4, [True] * 4) == [16] * 4
     assert bench.scatter_pass_bytes(64, 0, [True, False] * 4) == [16] * 4
 
 
 def test_whole_sort_bytes():
     assert bench.algorithmic_bytes_per_key(16, 0, [True, True]) == 4
-    assert bench.algorithmic_bytes_per_key(16, 4, [True, True]) == 2 + 2 * 12
+    # histogram read, both passes, the expansion's key write
+    assert bench.algorithmic_bytes_per_key(16, 4, [True, True]) == 2 + 11 + 9 + 2
+    # only the second pass: plus the high-byte copy (read 2, write 1)
+    assert bench.algorithmic_bytes_per_key(16, 4, [False, True]) == 2 + 9 + 2 + 3
+    assert bench.algorithmic_bytes_per_key(16, 4, [False, False]) == 2 + 8 + 2
     assert bench.algorithmic_bytes_per_key(32, 4, [True, True, False, False]) == 4 + 2 * 16
     assert bench.algorithmic_bytes_per_key(64, 8, [False] * 8) == 8 + 2 * 16
 

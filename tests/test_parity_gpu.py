@@ -216,11 +216,14 @@ def test_many_offset_levels_and_ragged_tail(gpu):
 
 def test_pair_sorts_with_one_active_digit_and_in_a_graph(gpu):
     """16-bit pair sorts above 2^22 keys, whose keys are expanded from the
-    2^16-bin prefix: only the second digit active (the low byte is
-    constant), only the first (the high byte is constant; that pass is then
-    the last and writes the keys too, the same values the expansion
-    writes), both; and the same sort captured into a hipGraph, replayed
-    twice with the outputs cleared in between."""
+    2^16-bin prefix and whose second pass sorts by the high key bytes the
+    first pass wrote: only the second digit active (the low byte is
+    constant, so the high bytes are copied from the input instead), only
+    the first (the high byte is constant; that pass is then the last and
+    writes only payloads), both; the same in signed descending order (the
+    copied bytes are those of the mapped keys), with 8-byte payloads (4096-key
+    tiles), and clobbering the input; and the sort captured into a
+    hipGraph, replayed twice with the outputs cleared in between."""
     n = (1 << 22) + 3
     rng = np.random.default_rng(5)
     idx = np.arange(n, dtype=np.uint32)
@@ -229,6 +232,22 @@ def test_pair_sorts_with_one_active_digit_and_in_a_graph(gpu):
              rng.integers(0, 65536, n).astype(np.uint16)]
     for keys in cases:
         ko, vo = fs.sort_pairs(dev(keys), dev(idx))
+        torch.cuda.synchronize()
+        ek, ev = oracle.sort(keys, idx)
+        assert np.array_equal(host(ko), ek)
+        assert np.array_equal(host(vo), ev)
+        ko, vo = fs.sort_pairs(dev(keys), dev(idx), key_type="signed", descending=True)
+        torch.cuda.synchronize()
+        ek, ev = oracle.sort_ordered(keys, idx, key_type="signed", descending=True)
+        assert np.array_equal(host(ko), ek)
+        assert np.array_equal(host(vo), ev)
+        idx8 = idx.astype(np.uint64) * np.uint64(0x100000001)
+        ko, vo = fs.sort_pairs(dev(keys), dev(idx8))
+        torch.cuda.synchronize()
+        ek, ev = oracle.sort(keys, idx8)
+        assert np.array_equal(host(ko), ek)
+        assert np.array_equal(host(vo), ev)
+        ko, vo = fs.sort_pairs(dev(keys), dev(idx), clobber=True)
         torch.cuda.synchronize()
         ek, ev = oracle.sort(keys, idx)
         assert np.array_equal(host(ko), ek)
