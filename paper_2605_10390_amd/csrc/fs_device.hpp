@@ -254,8 +254,8 @@ __device__ __forceinline__ T scan256_exclusive(T x, T* wsum, T* total) {
 // Returns (count of d before this item) + (peers below this lane).
 // FULL: every lane is valid (no lane masking at all).  The OR is waited for
 // before the word is read back, and the leader's writes before the next
-// item (a form that issues the reads right behind the OR, with no waits,
-// measured slower on spread keys).
+// item; without either wait the sort measured the same (the LDS runs a
+// wave's operations in order, so the waits are for pacing, not ordering).
 constexpr uint32_t kLgkmWait0 = 0xC07F;  // s_waitcnt lgkmcnt(0), other counters free
 template <bool FULL = false>
 __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint64_t* peers_w,

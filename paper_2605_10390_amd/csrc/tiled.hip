@@ -83,11 +83,9 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         // slot 0 is counted by the first read unless it sorts another digit
         if (pass == 0 && !a.plan[kPlanRecount0]) return;
         src = pass_source<K>(a, a.plan[4 * pass + 1]);
-        shift = 8 * (int)a.plan[4 * pass + 3];
-        if (sizeof(K) == 1 && a.narrow) {  // second pass of a 16-bit pair sort
-            src = reinterpret_cast<const K*>(a.narrow);
-            shift = 0;
-        }
+        // one-byte keys have a single digit (shift 0)
+        shift = sizeof(K) == 1 ? 0 : 8 * (int)a.plan[4 * pass + 3];
+        if (sizeof(K) == 1 && a.narrow) src = reinterpret_cast<const K*>(a.narrow);  // 16-bit pairs' second pass
     }
     const int tid = threadIdx.x, wave = tid >> 6, copy = wave % kHistCopies;
     for (int i = tid; i < 2 * TPS * kHistCopies * SETW; i += kTileHistThreads) (&s_t[0][0][0][0])[i] = 0;
@@ -664,7 +662,7 @@ void k_tile_scatter(TiledArgs a, int pass) {
     }
     K* sink_k = reinterpret_cast<K*>(a.sink);
     VS* sink_v = reinterpret_cast<VS*>(a.sink);
-    const int shift = narrow_src ? 0 : 8 * (int)a.plan[4 * pass + 3];
+    const int shift = sizeof(K) == 1 ? 0 : 8 * (int)a.plan[4 * pass + 3];  // one-byte keys: one digit
     // the high bytes matter only if the second pass runs
     const bool write_high = KOUT == kOutHigh && a.plan[4 * 1] != 0;
     uint8_t* sink_b = reinterpret_cast<uint8_t*>(a.sink);
