@@ -511,6 +511,33 @@ __device__ __forceinline__ void exp_hist(const SegCtx& x, ExpandShared& sm, cons
         for (int u = 0; u < U; ++u) {
             const uint64_t i = i0 + (uint64_t)u * kExpThreads + tid;
             const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+            if (ballot(i * 8 >= lead && i * 8 + 8 <= lead + n) == ballot(true)) {
+                // every lane's vector inside the range: an add of one per
+                // key; a carry needs a half that read 0xFFFF, so only then
+                // are the exact tests made
+                uint32_t kk[8], sft[8], old[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    kk[e] = (wv[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                    sft[e] = (kk[e] & 1u) << 4;
+                    old[e] = atomicAdd(&sm.cnt[kk[e] >> 1], 1u << sft[e]);
+                }
+                if (may_carry) {
+                    bool full = false;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) full |= ((old[e] >> sft[e]) & 0xFFFFu) == 0xFFFFu;
+                    if (__builtin_expect(full, 0)) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const uint32_t inc = 1u << sft[e];
+                            const bool word_wrap = old[e] + inc < old[e];
+                            const bool lo_wrap = (old[e] & 0xFFFFu) + (inc & 0xFFFFu) > 0xFFFFu;
+                            if (word_wrap || lo_wrap) exp_log(sm, kk[e] >> 1, (uint32_t)lo_wrap, (uint32_t)word_wrap);
+                        }
+                    }
+                }
+                continue;
+            }
             uint32_t w8[8], inc8[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -992,6 +1019,38 @@ __global__ __launch_bounds__(kSegTileThreads) void k_seg_hist(SegCtx x, int c) {
             for (int u = 0; u < U; ++u) {
                 const uint64_t i = i0 + (uint64_t)u * kSegTileThreads + tid;
                 const K* kv = reinterpret_cast<const K*>(&v[u]);
+                const uint64_t all = ballot(true);
+                if (ballot(i * VK >= lead && i * VK + VK <= lead + count) == all) {
+                    // every lane's vector inside the range: a digit whose
+                    // value differs across the wave's first keys (spread)
+                    // adds one per key; the others keep the whole-wave test
+                    uint32_t spread = 0;
+                    const K k0 = seg_map<ORD, K>(x, kv[0]);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        const uint32_t dg = digit_of<K>(k0, 8 * j);
+                        if (ballot(dg == __builtin_amdgcn_readfirstlane(dg)) != all) spread |= 1u << j;
+                    }
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const K key = seg_map<ORD, K>(x, kv[e]);
+#pragma unroll
+                        for (int j = 0; j < D; ++j) {
+                            const uint32_t dg = digit_of<K>(key, 8 * j);
+                            if ((spread >> j) & 1u) {
+                                atomicAdd(&cnt[j][dg], 1u);
+                            } else {
+                                const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                                if (ballot(dg == d0) == all) {
+                                    if (lanes_below(all) == 0) atomicAdd(&cnt[j][dg], popc64(all));
+                                } else {
+                                    atomicAdd(&cnt[j][dg], 1u);
+                                }
+                            }
+                        }
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int e = 0; e < VK; ++e) {
                     const uint64_t idx = i * VK + e;
@@ -1290,6 +1349,34 @@ __global__ __launch_bounds__(256) void k_seg_wg(SegCtx x, int c) {
                 for (int u = 0; u < U; ++u) {
                     const uint32_t i = i0 + u * THREADS + tid;
                     const K* kv = reinterpret_cast<const K*>(&v[u]);
+                    const uint64_t all = ballot(true);
+                    if (ballot(i < nv && i * VK >= lead && i * VK + VK <= lead + n) == all) {
+                        // whole vectors: digits that differ across the wave's
+                        // first keys add one per key (as in k_seg_hist)
+                        uint32_t spread = 0;
+                        const K k0 = seg_map<ORD, K>(x, kv[0]);
+#pragma unroll
+                        for (int j = 0; j < D; ++j) {
+                            const uint32_t dg = digit_of<K>(k0, 8 * j);
+                            if (ballot(dg == __builtin_amdgcn_readfirstlane(dg)) != all) spread |= 1u << j;
+                        }
+#pragma unroll
+                        for (int e = 0; e < VK; ++e) {
+                            const K ke = seg_map<ORD, K>(x, kv[e]);
+#pragma unroll
+                            for (int j = 0; j < D; ++j) {
+                                const uint32_t dg = digit_of<K>(ke, 8 * j);
+                                if ((spread >> j) & 1u) {
+                                    atomicAdd(&s_start[j][dg], 1u);
+                                } else if (ballot(dg == __builtin_amdgcn_readfirstlane(dg)) == all) {
+                                    if (lanes_below(all) == 0) atomicAdd(&s_start[j][dg], popc64(all));
+                                } else {
+                                    atomicAdd(&s_start[j][dg], 1u);
+                                }
+                            }
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int e = 0; e < VK; ++e) {
                         const uint32_t idx = i * VK + e;
