@@ -132,6 +132,29 @@ def test_unaligned_buffers(gpu):
         assert np.array_equal(host(out), oracle.sort(k[1:1 + n])), bits
 
 
+def test_unaligned_pair_buffers(gpu):
+    """16-bit pair sorts over views that start past a 16-byte boundary:
+    the first pass writes the high key bytes into the misaligned output
+    buffer and the second pass reads them back as one-byte keys, over many
+    8192-key tiles and a ragged tail, with 4- and 8-byte payloads, in
+    unsigned and in signed descending order."""
+    n = (1 << 20) + 12345
+    rng = np.random.default_rng(21)
+    k = rng.integers(0, 65536, n + 3).astype(np.uint16)
+    for vb in (4, 8):
+        v = rng.integers(0, 1 << 31, n + 3).astype(np.uint32 if vb == 4 else np.uint64)
+        kd, vd = dev(k)[1:1 + n], dev(v)[1:1 + n]
+        kob = torch.empty(n + 1, dtype=kd.dtype, device=gpu)
+        vob = torch.empty(n + 1, dtype=vd.dtype, device=gpu)
+        for key_type, desc in (("unsigned", False), ("signed", True)):
+            ko, vo = fs.sort_pairs(kd, vd, keys_out=kob[1:], vals_out=vob[1:], key_type=key_type,
+                                   descending=desc)
+            torch.cuda.synchronize()
+            ek, ev = oracle.sort_ordered(k[1:1 + n], v[1:1 + n], key_type=key_type, descending=desc)
+            assert np.array_equal(host(ko), ek), (vb, key_type)
+            assert np.array_equal(host(vo), ev), (vb, key_type)
+
+
 def test_all_equal_is_a_copy(gpu):
     n = 3 * 4096 + 5
     for bits in (16, 32, 64):
