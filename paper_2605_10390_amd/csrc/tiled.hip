@@ -638,6 +638,12 @@ void k_tile_scatter(TiledArgs a, int pass) {
     static_assert(THREADS >= kRadix, "one thread per digit value");
     static_assert(T < 65536, "tile counts are 16-bit");
     constexpr bool kLateVals = LATE;
+    // wide keys with payloads on LATE (8192-key) tiles: the payloads are
+    // fetched only once the tile's keys are staged in sorted order (their
+    // registers are free then) and go through the key buffer after the keys
+    // are stored, so the tile fits LDS twice per CU; the next tile's keys
+    // are requested while the payloads are stored
+    constexpr bool kSplit = kHasVals && LATE && sizeof(K) >= 4 && sizeof(VS) <= sizeof(K);
 
     __shared__ uint64_t s_peers[W][kRadix];
     __shared__ uint32_t s_wcnt[W][kRadix];
@@ -645,7 +651,7 @@ void k_tile_scatter(TiledArgs a, int pass) {
     __shared__ uint64_t s_wsum[4];
     __shared__ uint32_t s_next;
     __shared__ __attribute__((aligned(16))) K s_keys[NV * VK];  // slot T: sink of a bad rank
-    __shared__ VS s_vals[kHasVals ? T + 1 : 1];
+    __shared__ VS s_vals[kHasVals && !kSplit ? T + 1 : 1];
 
     if (!a.plan[4 * pass]) return;
     const uint32_t src_sel = a.plan[4 * pass + 1], dst_sel = a.plan[4 * pass + 2];
@@ -729,7 +735,7 @@ void k_tile_scatter(TiledArgs a, int pass) {
     if (t < thi) {
         if (tid == 0) ticket = atomicAdd(ctr, 1u);
         fetch_keys(t);
-        fetch_vals(t);
+        if constexpr (!kSplit) fetch_vals(t);
         // drain the first requests here, so that at the top of the loop only
         // the previous tile's stores can be outstanding (vmcnt(0))
         __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -827,15 +833,20 @@ void k_tile_scatter(TiledArgs a, int pass) {
                     bad_rank |= pos >= (uint32_t)T;
                     const uint32_t p = pos < (uint32_t)T ? pos : (uint32_t)T;
                     s_keys[p] = kk;
-                    if constexpr (kHasVals) s_vals[p] = kLateVals ? nval[k] : val[k];
+                    if constexpr (kSplit) kr[k] = p;  // the payload's slot
+                    else if constexpr (kHasVals) s_vals[p] = kLateVals ? nval[k] : val[k];
                 }
             }
-            if constexpr (kLateVals) {
+            if constexpr (kSplit) {
+                __builtin_amdgcn_sched_barrier(0);  // not above the key staging
+                fetch_vals(t);  // this tile's payloads, staged after its keys are stored
+            } else if constexpr (kLateVals) {
                 fetch_keys(more ? tn : t);
                 fetch_vals(more ? tn : t);
             }
             __syncthreads();
 
+            uint32_t dg[kSplit ? (ITEMS + 3) / 4 : 1];  // digits of this thread's slots (split staging)
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const uint32_t q = k * THREADS + tid;
@@ -850,9 +861,35 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 if constexpr (KOUT == kOutHigh) {  // the mapped key's high byte
                     if (write_high) *(ok ? a.narrow + dst : sink_b) = (uint8_t)((uint32_t)kk >> 8);
                 }
-                if constexpr (kHasVals) *(ok ? dst_v + dst : sink_v) = s_vals[qq];
+                if constexpr (kSplit) {
+                    if (k % 4 == 0) dg[k / 4] = 0;
+                    dg[k / 4] |= digit_of<K>(kk, shift) << (8 * (k % 4));
+                } else if constexpr (kHasVals) {
+                    *(ok ? dst_v + dst : sink_v) = s_vals[qq];
+                }
                 // keep the compiler from hoisting every slot's loads at once
                 if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (kSplit) {
+                // the payloads, through the key buffer at their keys' slots
+                VS* s_pv = reinterpret_cast<VS*>(s_keys);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k)
+                    if (wbase + k * kWave + lane < count) s_pv[kr[k]] = nval[k];
+                // the next tile's keys, in flight while the payloads are stored
+                fetch_keys(more ? tn : t);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const uint32_t q = k * THREADS + tid;
+                    const bool in = q < count;
+                    const uint32_t qq = in ? q : 0u;
+                    const uint64_t dst = s_dst[(dg[k / 4] >> (8 * (k % 4))) & 0xFFu] + qq;
+                    const bool ok = in && dst < a.n;
+                    *(ok ? dst_v + dst : sink_v) = s_pv[qq];
+                    if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
             }
             __syncthreads();
             if (!more) break;
@@ -1159,7 +1196,7 @@ hipError_t launch_trie_fixup(const TiledArgs& a, int key_bytes, int val_bytes, h
     X(uint16_t, uint32_t, 512, 16, true)   \
     X(uint16_t, uint64_t, 512, 8, false)   \
     X(uint32_t, NoVal, 512, 8, false)      \
-    X(uint32_t, uint32_t, 512, 8, false)   \
+    X(uint32_t, uint32_t, 512, 16, true)   \
     X(uint32_t, uint64_t, 512, 8, false)   \
     X(uint64_t, NoVal, 512, 8, false)      \
     X(uint64_t, uint32_t, 512, 8, false)   \
@@ -1210,6 +1247,7 @@ hipError_t launch_tile_hist(const TiledArgs& a, int key_bytes, int pass, uint32_
     else if (key_bytes == 2 && a.tile == 8192) launch_hist_t<uint16_t, 8192>(a, pass, first, groups, s);
     else if (key_bytes == 2 && a.tile == 16384) launch_hist_t<uint16_t, 16384>(a, pass, first, groups, s);
     else if (key_bytes == 4 && a.tile == 4096) launch_hist_t<uint32_t, 4096>(a, pass, first, groups, s);
+    else if (key_bytes == 4 && a.tile == 8192) launch_hist_t<uint32_t, 8192>(a, pass, first, groups, s);
     else if (key_bytes == 4 && a.tile == 2048) launch_hist_t<uint32_t, 2048>(a, pass, first, groups, s);
     else if (key_bytes == 8 && a.tile == 4096) launch_hist_t<uint64_t, 4096>(a, pass, first, groups, s);
     else if (key_bytes == 8 && a.tile == 2048) launch_hist_t<uint64_t, 2048>(a, pass, first, groups, s);
