@@ -1195,7 +1195,7 @@ hipError_t launch_trie_fixup(const TiledArgs& a, int key_bytes, int val_bytes, h
     X(uint8_t, uint64_t, 512, 8, false)    \
     X(uint16_t, uint32_t, 512, 16, true)   \
     X(uint16_t, uint64_t, 512, 8, false)   \
-    X(uint32_t, NoVal, 512, 8, false)      \
+    X(uint32_t, NoVal, 512, 16, true)      \
     X(uint32_t, uint32_t, 512, 16, true)   \
     X(uint32_t, uint64_t, 512, 8, false)   \
     X(uint64_t, NoVal, 512, 8, false)      \
