@@ -64,6 +64,18 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__builtin_popcountll(m); }
 
+// A wave-uniform value that the optimiser must treat as new on every loop
+// iteration.  A tile's alignment shift is the same for every tile (tile
+// bases are multiples of the vector width), and the compiler would
+// otherwise hoist every per-element index derived from it out of the tile
+// loop and hold them all in registers for the loop's length (about 100
+// VGPRs in the one-byte histogram, which then ran one workgroup per CU).
+// No instruction is emitted.
+__device__ __forceinline__ uint32_t each_iteration(uint32_t x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

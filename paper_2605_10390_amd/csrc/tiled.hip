@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kTileHistThreads) void k_tile_hist(TiledArgs a, int
         const uint32_t cnt = (uint32_t)(hi - lo);
         // the step's keys [lo, hi) lie in the aligned vectors starting at key
         // index lo - sh
-        const uint32_t sh = (uint32_t)((lo + head) % VK);
+        const uint32_t sh = each_iteration((uint32_t)((lo + head) % VK));
         const uint32_t nv = (sh + cnt + VK - 1) / VK;
         const u32x4* gv = reinterpret_cast<const u32x4*>(src + (lo - sh));
         // all of the step's loads first, then the counting
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kHist16Threads) void k_tile_hist16(TiledArgs a, uin
         const uint64_t hi_t = t0 + TPS < thi ? t0 + TPS : thi;
         const uint64_t hi = hi_t * TILE < a.n ? hi_t * TILE : a.n;
         const uint32_t cntk = (uint32_t)(hi - lo);
-        const uint32_t sh = (uint32_t)((lo + head) % VK);
+        const uint32_t sh = each_iteration((uint32_t)((lo + head) % VK));
         const uint32_t nv = (sh + cntk + VK - 1) / VK;
         u32x4 q[HV + 1];
 #pragma unroll
