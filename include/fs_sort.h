@@ -147,10 +147,11 @@ fs_status fs_sort_keys_noalloc(const void *keys_in, void *keys_out, uint64_t n, 
  *   vals_in/vals_out  device, n values of val_bytes bytes (4 or 8).
  * None of the four ranges may overlap another.  flags: FS_FLAG_CLOBBER_INPUT
  * (keys_in and vals_in may then be overwritten) and the key order, as for
- * fs_sort_keys.  For 16-bit keys the keys of the last pass are never
- * stored (they are written from the 2^16-bin histogram), so the first pass
- * uses keys_out as its key buffer and the workspace holds no key copy even
- * without CLOBBER_INPUT.
+ * fs_sort_keys.  For 16-bit keys the passes never store whole keys: the
+ * first keeps only each key's high byte (one byte per key, in the
+ * workspace) for the second, and the sorted keys are written from the
+ * 2^16-bin histogram, so the workspace holds no key copy even without
+ * CLOBBER_INPUT.
  */
 fs_status fs_sort_pairs(const void *keys_in, void *keys_out, const void *vals_in, void *vals_out,
                         uint64_t n, int key_bits, int val_bytes, unsigned flags,

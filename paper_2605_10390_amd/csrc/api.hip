@@ -86,11 +86,13 @@ SortLayout sort_layout(uint64_t n, int key_bytes, int val_bytes, int num_cus, bo
             L.wrap = take(4ull * 2 * kHist16Words);
             L.h16 = take(8ull * 65536);
             L.p16 = take(8ull * 65537);
+            // the keys' high bytes between the passes (one byte per key)
+            L.narrow = take((size_t)n);
         }
         // the passes' second buffer: none with clobber (the input serves);
         // none for the keys of a 16-bit pair sort (its first pass writes
-        // only their high bytes, into the output, which the second pass
-        // reads and the expansion from the histogram then overwrites)
+        // only their high bytes, which the second pass reads, and the
+        // sorted keys are expanded from the histogram)
         L.clobber = clobber;
         if (!clobber && !L.pairs16) L.tmp_keys = take((size_t)n * key_bytes);
         if (!clobber && val_bytes) L.tmp_vals = take((size_t)n * val_bytes);
@@ -257,11 +259,12 @@ static fs_status sort_impl(const void* keys_in, void* keys_out, const void* vals
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_merge16(part16, L.hist16_groups, wrap, wrap + kHist16Words, h16, s));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_plan_from16(h16, n, hist, base, plan, s, L.clobber));
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_scan16(h16, p16, s));
-        // pass 0 writes the payloads and, into the output key buffer, the
-        // high byte of every mapped key; pass 1 (when it runs, the last)
-        // sorts the payloads by those bytes, read as one-byte keys that
-        // need no further mapping
-        a.narrow = static_cast<uint8_t*>(keys_out);
+        // pass 0 writes the payloads and, into the workspace, the high byte
+        // of every mapped key; pass 1 (when it runs, the last) sorts the
+        // payloads by those bytes, read as one-byte keys that need no
+        // further mapping.  (With those bytes in the output key buffer
+        // instead, 2^30 pairs with 8-byte payloads measured 6% slower.)
+        a.narrow = reinterpret_cast<uint8_t*>(w + L.narrow);
         TiledArgs an = a;
         an.ord_pos = an.ord_neg = 0;
         FS_LAUNCH(FS_KERNEL_PLAN, 0, launch_tile_offsets(a, 0, s));

@@ -34,7 +34,7 @@ struct SortLayout {
     uint64_t tiles = 0, tile_blocks = 0, tile_supers = 0;
     size_t err = 0, plan = 0, hist = 0, base = 0, part = 0, wrap = 0, h16 = 0, p16 = 0, th = 0, bsum = 0,
            ssum = 0, sbase = 0, tile_tickets = 0, sink = 0, part16 = 0, tmp_keys = 0, tmp_vals = 0, total = 0,
-           trie_list = 0, trie_count = 0;
+           trie_list = 0, trie_count = 0, narrow = 0;
 };
 
 // clobber: the input arrays are the passes' second buffer (no temporary copy)

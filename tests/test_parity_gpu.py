@@ -237,6 +237,29 @@ def test_many_offset_levels_and_ragged_tail(gpu):
     assert np.array_equal(host(vo), ev)
 
 
+@pytest.mark.parametrize("n", [5, 4097, 3 * 8192 + 11, (1 << 20) + 7])
+def test_pairs16_keys_far_apart(gpu, n):
+    """16-bit pair sorts whose keys take a few values far apart (0, 3,
+    40000, 65535): the sorted keys are written from the 2^16-bin prefix
+    across long runs of empty bins, within one 8-key chunk and across
+    chunks; ascending unsigned and descending signed, 4- and 8-byte
+    payloads."""
+    rng = np.random.default_rng(n)
+    keys = np.array([0, 3, 40000, 65535], dtype=np.uint16)[rng.integers(0, 4, n)]
+    ws = fs.Workspace(gpu)
+    for vb in (4, 8):
+        v = _vals(n, vb, n + vb)
+        ko, vo = fs.sort_pairs(dev(keys), dev(v), workspace=ws)
+        torch.cuda.synchronize()
+        assert ws.error_word() == 0
+        ek, ev = oracle.sort(keys, v)
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (n, vb)
+        ko, vo = fs.sort_pairs(dev(keys), dev(v), workspace=ws, key_type="signed", descending=True)
+        torch.cuda.synchronize()
+        ek, ev = oracle.sort_ordered(keys, v, key_type="signed", descending=True)
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (n, vb, "signed desc")
+
+
 def test_pair_sorts_with_one_active_digit_and_in_a_graph(gpu):
     """16-bit pair sorts above 2^22 keys, whose keys are expanded from the
     2^16-bin prefix and whose second pass sorts by the high key bytes the
