@@ -237,6 +237,35 @@ def test_many_offset_levels_and_ragged_tail(gpu):
     assert np.array_equal(host(vo), ev)
 
 
+@pytest.mark.parametrize("vb", [0, 4, 8])
+@pytest.mark.parametrize("n", [5 * 4096 + 123, 70001])
+def test_u64_runs_of_equal_keys(gpu, n, vb):
+    """64-bit keys in runs of 601 equal keys, so that a 4096-key tile holds
+    at most 8 digit values and writes four staged slots at a time, with
+    runs starting at every offset modulo 4 (four-slot groups that straddle
+    a digit boundary) and a ragged last tile: ascending runs (every pass
+    sees the runs) and runs of hashed values (the first pass does), in
+    ascending unsigned and descending signed order."""
+    i = np.arange(n, dtype=np.uint64) // np.uint64(601)
+    cases = [i * np.uint64(0x0101010101010101),
+             (i + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)]
+    ws = fs.Workspace(gpu)
+    for keys in cases:
+        v = _vals(n, vb, n + vb) if vb else None
+        for kt, desc in (("unsigned", False), ("signed", True)):
+            if vb:
+                ko, vo = fs.sort_pairs(dev(keys), dev(v), workspace=ws, key_type=kt, descending=desc)
+                ek, ev = oracle.sort_ordered(keys, v, key_type=kt, descending=desc)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(vo), ev), (n, vb, kt)
+            else:
+                ko = fs.sort_keys(dev(keys), workspace=ws, key_type=kt, descending=desc)
+                ek = oracle.sort_ordered(keys, key_type=kt, descending=desc)
+                torch.cuda.synchronize()
+            assert ws.error_word() == 0
+            assert np.array_equal(host(ko), ek), (n, vb, kt)
+
+
 @pytest.mark.parametrize("n", [5, 4097, 3 * 8192 + 11, (1 << 20) + 7])
 def test_pairs16_keys_far_apart(gpu, n):
     """16-bit pair sorts whose keys take a few values far apart (0, 3,
