@@ -941,8 +941,10 @@ void k_tile_scatter(TiledArgs a, int pass) {
                 }
                 // keep the compiler from hoisting every slot's loads at once
                 // (a barrier every 8 slots measured 0.1-0.5% faster than
-                // every 4 on 2^31-key sorts; every 2, slower)
-                if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                // every 4 on 2^31-key sorts of 16- and 32-bit keys, every 2
+                // slower; 64-bit keys measured 1% faster with every 4)
+                constexpr int kSchedEvery = sizeof(K) == 8 ? 4 : 8;
+                if (k % kSchedEvery == kSchedEvery - 1) __builtin_amdgcn_sched_barrier(0);
             }
             if constexpr (kSplit) {
                 // the payloads, through the key buffer at their keys' slots
